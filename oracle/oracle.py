@@ -1,0 +1,141 @@
+"""ctypes wrapper around the C oracle (mtgp_oracle.c, f2.c) -- test infrastructure only.
+
+Builds liborc.so with gcc (no fast-math, no FP contraction) on first use or
+via build(). See mtgp_oracle.c for the definitions followed.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborc.so")
+SOURCES = [os.path.join(HERE, "mtgp_oracle.c"), os.path.join(HERE, "f2.c")]
+
+U32 = 0
+F12 = 1
+F01 = 2
+
+
+def build(force: bool = True) -> str:
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+           "-Wall", "-Wextra", "-o", tmp] + SOURCES
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("mexp", ctypes.c_uint32), ("pos", ctypes.c_uint32),
+                ("sh1", ctypes.c_uint32), ("sh2", ctypes.c_uint32),
+                ("param_tbl", ctypes.c_uint32 * 16), ("temper_tbl", ctypes.c_uint32 * 16)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.orc_nwords.argtypes = [ctypes.c_uint32]
+        L.orc_nwords.restype = ctypes.c_uint32
+        L.orc_seed.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+        L.orc_seed.restype = None
+        L.orc_generate.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_void_p, ctypes.c_uint64,
+                                   ctypes.c_int, ctypes.c_void_p]
+        L.orc_generate.restype = ctypes.c_int
+        L.orc_advance.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_void_p, ctypes.c_uint64]
+        L.orc_advance.restype = ctypes.c_int
+        L.orc_output_bits.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_void_p, ctypes.c_uint64,
+                                      ctypes.c_int, ctypes.c_void_p]
+        L.orc_output_bits.restype = ctypes.c_int
+        L.orc_bm.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        L.orc_bm.restype = ctypes.c_int64
+        L.orc_irreducible_prime_degree.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.orc_irreducible_prime_degree.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def to_c(ps) -> OrcParams:
+    p = OrcParams()
+    p.mexp, p.pos, p.sh1, p.sh2 = ps.mexp, ps.pos, ps.sh1, ps.sh2
+    for i in range(16):
+        p.param_tbl[i] = ps.param_tbl[i]
+        p.temper_tbl[i] = ps.temper_tbl[i]
+    return p
+
+
+def nwords(mexp: int) -> int:
+    return int(lib().orc_nwords(mexp))
+
+
+def seed_state(seed: int, mexp: int) -> np.ndarray:
+    n = nwords(mexp)
+    st = np.zeros(n, dtype=np.uint32)
+    lib().orc_seed(seed & 0xFFFFFFFF, n, st.ctypes.data)
+    return st
+
+
+def generate(ps, state: np.ndarray, n: int, kind: int = U32) -> np.ndarray:
+    """Generate n outputs; `state` (uint32[N], sequence order) is advanced in place."""
+    assert state.dtype == np.uint32 and state.flags.c_contiguous
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    rc = lib().orc_generate(ctypes.byref(to_c(ps)), state.ctypes.data, n, kind, out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected parameters (rc={rc})")
+    return out[:n]
+
+
+def advance(ps, state: np.ndarray, n: int) -> None:
+    rc = lib().orc_advance(ctypes.byref(to_c(ps)), state.ctypes.data, n)
+    if rc != 0:
+        raise ValueError(f"oracle rejected parameters (rc={rc})")
+
+
+def stream(ps, seed: int, n: int, kind: int = U32):
+    """(outputs, final state) of a fresh generator seeded with `seed`."""
+    st = seed_state(seed, ps.mexp)
+    out = generate(ps, st, n, kind)
+    return out, st
+
+
+def output_bits(ps, state: np.ndarray, n: int, bit: int) -> np.ndarray:
+    bits = np.zeros(n, dtype=np.uint8)
+    rc = lib().orc_output_bits(ctypes.byref(to_c(ps)), state.ctypes.data, n, bit, bits.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected parameters (rc={rc})")
+    return bits
+
+
+def berlekamp_massey(bits: Sequence[int]):
+    """(L, connection polynomial as uint8 array c[0..L])."""
+    b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8))
+    conn = np.zeros(len(b) + 2, dtype=np.uint8)
+    L = lib().orc_bm(b.ctypes.data, len(b), conn.ctypes.data)
+    if L < 0:
+        raise MemoryError
+    return int(L), conn[: L + 1].copy()
+
+
+def char_poly_from_conn(conn: np.ndarray) -> np.ndarray:
+    """Reciprocal of the connection polynomial: phi(x) = x^L C(1/x), as coeffs phi[0..L]."""
+    return conn[::-1].copy()
+
+
+def irreducible_prime_degree(phi: np.ndarray) -> bool:
+    phi = np.ascontiguousarray(np.asarray(phi, dtype=np.uint8))
+    rc = lib().orc_irreducible_prime_degree(phi.ctypes.data, len(phi) - 1)
+    if rc < 0:
+        raise ValueError("bad polynomial")
+    return rc == 1
