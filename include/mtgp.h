@@ -1,0 +1,178 @@
+/*
+ * mtgp.h -- C ABI of the MTGP library for AMD Instinct MI355X (gfx950).
+ *
+ * MTGP (Saito & Matsumoto, "Variants of Mersenne Twister Suitable for Graphic
+ * Processors") is an F2-linear generator whose state is N = ceil(p/32) 32-bit
+ * words for a Mersenne exponent p (section 3.3); each new word is
+ *     x_{N+i} = g(x_{M+i}, x_{1+i}, x_i)            (section 3.6, Definition
+ *                                                      "recursion parameters")
+ * and each output is tempered with x_{M-1+i}        (section 3.7, Definition
+ *                                                      "tempering parameter").
+ * Outputs are produced on the GPU by evaluating up to N-M mutually independent
+ * steps of the recursion at once (section 3.2).
+ *
+ * Conventions for every call below:
+ *   - Device pointers (`out`) are caller-owned device memory (e.g. a torch
+ *     tensor's data pointer) of at least 4*n bytes, 4-byte aligned.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Generation calls are asynchronous and stream-ordered; calls on one
+ *     handle must be issued in order on one stream, or the caller must
+ *     synchronise when switching streams. Handles are not thread-safe;
+ *     distinct handles are independent.
+ *   - Output k of a fresh generator is o_{N+k}: the N seed words are never
+ *     emitted. All output kinds share one position counter: k outputs of any
+ *     kind advance the stream by k steps, and the float outputs at position k
+ *     are derived from the uint32 output at position k (section 6).
+ *   - Any n >= 0 is allowed; n = 0 is a successful no-op. Consecutive calls
+ *     continue the stream exactly (section 8): gen(a) then gen(b) equals the
+ *     first a+b outputs of gen(a+b).
+ *   - Return codes: MTGP_OK, or a negative MTGP_E* code. On MTGP_EDEVICE the
+ *     stream position is not advanced. mtgp_last_error() holds the code of
+ *     the last failing call on the calling thread.
+ */
+#ifndef MTGP_H
+#define MTGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MTGP_OK        0
+#define MTGP_EINVAL   (-1)   /* bad parameter set, bad argument or alignment */
+#define MTGP_ENOMEM   (-2)   /* host or device allocation failed */
+#define MTGP_EDEVICE  (-3)   /* HIP runtime error; stream position unchanged */
+
+/* Output kinds (section 6). */
+#define MTGP_KIND_UINT32        0   /* tempered 32-bit word o_{N+k} */
+#define MTGP_KIND_FLOAT32_1TO2  1   /* bits 0x3f800000 | (o >> 9): float in [1,2) */
+#define MTGP_KIND_FLOAT32_0TO1  2   /* the [1,2) value minus 1.0f: float in [0,1) */
+
+/*
+ * Parameter set (section 3.6 and 3.7). Copied at create time; the caller
+ * keeps ownership.
+ *   mexp       Mersenne exponent p; N = ceil(p/32), r = 32N - p. Accepted:
+ *              65 <= p <= 65536 (3 <= N <= 2048). The released periods are
+ *              p = 11213, 23209, 44497 (N = 351, 726, 1391).
+ *   pos        middle position M, 2 <= M <= N-1 (section 3.1 requires 1<M<N;
+ *              M >= 2 keeps the tempering word x_{M-1+i} a full state word).
+ *   sh1, sh2   shift amounts, 0..31.
+ *   param_tbl  recursion table: entry v is (v as a 4-bit row vector) * R for
+ *              the 4x32 matrix R. Must be F2-linear: tbl[0] = 0 and
+ *              tbl[a ^ b] = tbl[a] ^ tbl[b].
+ *   temper_tbl tempering table, entry v = (v as a 4-bit row vector) * T; same
+ *              linearity rule.
+ */
+typedef struct mtgp_param_set {
+    uint32_t mexp;
+    uint32_t pos;
+    uint32_t sh1;
+    uint32_t sh2;
+    uint32_t param_tbl[16];
+    uint32_t temper_tbl[16];
+} mtgp_param_set;
+
+typedef struct mtgp mtgp_t;               /* one generator; owns its device state */
+typedef struct mtgp_batch mtgp_batch_t;   /* many generators; states resident in one device array */
+
+/* Number of state words N for a Mersenne exponent (0 if outside 65..65536). */
+uint32_t mtgp_state_words(uint32_t mexp);
+
+/*
+ * Create a generator on the current HIP device. The state x_0..x_{N-1} is
+ * seeded on the host (the paper leaves seeding open; the MT19937
+ * initialisation recurrence x_0 = seed, x_i = 1812433253 (x_{i-1} ^
+ * (x_{i-1} >> 30)) + i is used) and copied to device memory owned by the
+ * handle. Returns NULL on error (see mtgp_last_error()).
+ */
+mtgp_t *mtgp_create(const mtgp_param_set *ps, uint32_t seed);
+
+/*
+ * Generate n outputs into device memory `out` on `stream` (section 8: load
+ * the state, run rounds of the recursion, store outputs, store the state
+ * back). One kernel launch with one workgroup.
+ */
+int mtgp_generate_uint32(mtgp_t *g, size_t n, uint32_t *out, void *stream);
+int mtgp_generate_float32_1to2(mtgp_t *g, size_t n, float *out, void *stream);
+int mtgp_generate_float32_0to1(mtgp_t *g, size_t n, float *out, void *stream);
+
+/* Release the handle (NULL-safe); waits for work queued on its last stream. */
+void mtgp_destroy(mtgp_t *g);
+
+/*
+ * Checkpoint / restore. get_state waits for the last stream used, then copies
+ * the N state words x_c..x_{c+N-1} (sequence order) to host memory and the
+ * number c of outputs produced so far to *consumed (may be NULL).
+ * set_state installs N words (any values; the r low bits of word 0 are
+ * ignored by the recursion) and a position counter.
+ */
+int mtgp_get_state(mtgp_t *g, uint32_t *host_words, uint64_t *consumed);
+int mtgp_set_state(mtgp_t *g, const uint32_t *host_words, uint64_t consumed);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent generators (section 4.3 runs one block per
+ * generator with distinct parameter sets; here one persistent launch serves
+ * a list of requests of uneven length, ordered longest first).
+ * ------------------------------------------------------------------------- */
+
+/* One request: `n` outputs of `kind` from generator `gen` into device `out`. */
+typedef struct mtgp_request {
+    uint32_t gen;
+    uint32_t kind;
+    uint64_t n;
+    void *out;
+} mtgp_request;
+
+/*
+ * Create `count` generators from ps[0..count-1] (each validated as for
+ * mtgp_create) seeded with seeds[0..count-1]. All states live in one device
+ * array that stays resident until mtgp_batch_destroy.
+ */
+mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds, uint32_t count);
+
+/*
+ * Serve `nreq` requests in one persistent kernel launch on `stream`. A
+ * generator may appear at most once per call (requests for one generator
+ * must be split across calls, which run in stream order). Requests with
+ * n = 0 are skipped. Returns MTGP_EINVAL for a bad generator index, kind,
+ * duplicate generator or misaligned output.
+ */
+int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream);
+
+/*
+ * Same work as mtgp_batch_generate, but as one launch per request on
+ * `stream` (the plain form, for comparison).
+ */
+int mtgp_batch_generate_plain(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream);
+
+int mtgp_batch_get_state(mtgp_batch_t *b, uint32_t gen, uint32_t *host_words, uint64_t *consumed);
+int mtgp_batch_set_state(mtgp_batch_t *b, uint32_t gen, const uint32_t *host_words, uint64_t consumed);
+uint32_t mtgp_batch_size(const mtgp_batch_t *b);
+void mtgp_batch_destroy(mtgp_batch_t *b);
+
+/* ---------------------------------------------------------------------------
+ * Launch shape (for tuning; results are identical for every valid shape).
+ *   mode 0: one workgroup of `threads` lanes per generator, `spl` steps per
+ *           lane per round (spl in {1, 2, 4}), a barrier between rounds.
+ *   mode 1: one wavefront per generator, `threads`/64 wavefronts per
+ *           workgroup, spl in {1, 2, 4, 6, 8, 12, 16}, no barriers.
+ * A round computes W = min(N - M, lanes * spl) steps (section 3.2), lanes =
+ * threads (mode 0) or 64 (mode 1). lds_words is the LDS window per generator
+ * (0 = automatic; must be >= 2N + W for every generator served) and grid the
+ * number of workgroups (0 = automatic). mode < 0 restores the automatic
+ * choice. Returns MTGP_EINVAL for an unsupported shape.
+ * ------------------------------------------------------------------------- */
+int mtgp_batch_set_launch(mtgp_batch_t *b, int mode, int threads, int spl, int lds_words, int grid);
+int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words);
+
+/* Code of the last failing call on this thread, and a message for a code. */
+int mtgp_last_error(void);
+const char *mtgp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTGP_H */

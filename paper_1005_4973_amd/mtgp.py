@@ -1,0 +1,244 @@
+"""Python binding of libmtgp.so (include/mtgp.h): argument marshalling only.
+
+Every generation step runs in the HIP kernels of libmtgp.so; this module only
+passes torch tensor pointers and torch streams through the C ABI. It raises
+if the library has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import torch  # loads torch's HIP runtime first, so the library shares it
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmtgp.so")
+
+MTGP_OK = 0
+MTGP_EINVAL = -1
+MTGP_ENOMEM = -2
+MTGP_EDEVICE = -3
+
+KIND_UINT32 = 0
+KIND_FLOAT32_1TO2 = 1
+KIND_FLOAT32_0TO1 = 2
+
+
+class MTGPError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class ParamSetC(ctypes.Structure):
+    _fields_ = [("mexp", ctypes.c_uint32), ("pos", ctypes.c_uint32),
+                ("sh1", ctypes.c_uint32), ("sh2", ctypes.c_uint32),
+                ("param_tbl", ctypes.c_uint32 * 16), ("temper_tbl", ctypes.c_uint32 * 16)]
+
+
+class RequestC(ctypes.Structure):
+    _fields_ = [("gen", ctypes.c_uint32), ("kind", ctypes.c_uint32),
+                ("n", ctypes.c_uint64), ("out", ctypes.c_void_p)]
+
+
+# Every symbol the header declares, with its ctypes signature.
+_SIGNATURES = {
+    "mtgp_state_words": (ctypes.c_uint32, [ctypes.c_uint32]),
+    "mtgp_create": (ctypes.c_void_p, [ctypes.POINTER(ParamSetC), ctypes.c_uint32]),
+    "mtgp_generate_uint32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_generate_float32_1to2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_generate_float32_0to1": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_destroy": (None, [ctypes.c_void_p]),
+    "mtgp_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "mtgp_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
+    "mtgp_batch_create": (ctypes.c_void_p, [ctypes.POINTER(ParamSetC), ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_batch_generate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p]),
+    "mtgp_batch_generate_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p]),
+    "mtgp_batch_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "mtgp_batch_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64]),
+    "mtgp_batch_size": (ctypes.c_uint32, [ctypes.c_void_p]),
+    "mtgp_batch_destroy": (None, [ctypes.c_void_p]),
+    "mtgp_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 5),
+    "mtgp_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 4),
+    "mtgp_last_error": (ctypes.c_int, []),
+    "mtgp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1005_4973_amd/build.py "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().mtgp_strerror(code).decode()
+    except RuntimeError:
+        return str(code)
+
+
+def state_words(mexp: int) -> int:
+    return int(lib().mtgp_state_words(mexp))
+
+
+def _param_c(ps) -> ParamSetC:
+    p = ParamSetC()
+    p.mexp, p.pos, p.sh1, p.sh2 = ps.mexp, ps.pos, ps.sh1, ps.sh2
+    for i in range(16):
+        p.param_tbl[i] = ps.param_tbl[i]
+        p.temper_tbl[i] = ps.temper_tbl[i]
+    return p
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != MTGP_OK:
+        raise MTGPError(rc, what)
+
+
+_DTYPE = {KIND_UINT32: torch.int32, KIND_FLOAT32_1TO2: torch.float32, KIND_FLOAT32_0TO1: torch.float32}
+_GEN_FN = {KIND_UINT32: "mtgp_generate_uint32", KIND_FLOAT32_1TO2: "mtgp_generate_float32_1to2",
+           KIND_FLOAT32_0TO1: "mtgp_generate_float32_0to1"}
+
+
+def _out_tensor(n: int, kind: int, out: Optional[torch.Tensor], device) -> torch.Tensor:
+    if out is None:
+        return torch.empty(n, dtype=_DTYPE[kind], device=device)
+    if not out.is_cuda or out.element_size() != 4 or not out.is_contiguous() or out.numel() < n:
+        raise ValueError("out must be a contiguous 4-byte CUDA tensor with at least n elements")
+    return out
+
+
+class Generator:
+    """One MTGP generator (mtgp_create). Outputs land in torch tensors."""
+
+    def __init__(self, ps, seed: int):
+        self.ps = ps
+        self._h = lib().mtgp_create(ctypes.byref(_param_c(ps)), seed & 0xFFFFFFFF)
+        if not self._h:
+            raise MTGPError(lib().mtgp_last_error(), "mtgp_create")
+        self.nwords = state_words(ps.mexp)
+
+    def generate(self, n: int, kind: int = KIND_UINT32, out: Optional[torch.Tensor] = None,
+                 stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        out = _out_tensor(n, kind, out, "cuda")
+        rc = getattr(lib(), _GEN_FN[kind])(self._h, n, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        _check(rc, _GEN_FN[kind])
+        return out[:n] if out.numel() != n else out
+
+    def generate_uint32(self, n, out=None, stream=None):
+        return self.generate(n, KIND_UINT32, out, stream)
+
+    def generate_float32_1to2(self, n, out=None, stream=None):
+        return self.generate(n, KIND_FLOAT32_1TO2, out, stream)
+
+    def generate_float32_0to1(self, n, out=None, stream=None):
+        return self.generate(n, KIND_FLOAT32_0TO1, out, stream)
+
+    def set_launch(self, mode: int = -1, threads: int = 0, spl: int = 1, lds_words: int = 0):
+        """Override the launch shape (mode -1 restores the automatic choice)."""
+        _check(lib().mtgp_set_launch(self._h, mode, threads, spl, lds_words), "mtgp_set_launch")
+
+    def get_state(self):
+        import numpy as np
+        words = np.zeros(self.nwords, dtype=np.uint32)
+        consumed = ctypes.c_uint64(0)
+        _check(lib().mtgp_get_state(self._h, words.ctypes.data, ctypes.byref(consumed)), "mtgp_get_state")
+        return words, consumed.value
+
+    def set_state(self, words, consumed: int = 0):
+        import numpy as np
+        w = np.ascontiguousarray(np.asarray(words, dtype=np.uint32))
+        if w.size != self.nwords:
+            raise ValueError("state must have N words")
+        _check(lib().mtgp_set_state(self._h, w.ctypes.data, consumed), "mtgp_set_state")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mtgp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many resident generators (mtgp_batch_create); one persistent launch per call."""
+
+    def __init__(self, params: Sequence, seeds: Sequence[int]):
+        import numpy as np
+        if len(params) != len(seeds) or len(params) == 0:
+            raise ValueError("params and seeds must be non-empty and of equal length")
+        arr = (ParamSetC * len(params))(*[_param_c(p) for p in params])
+        sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint32))
+        self._h = lib().mtgp_batch_create(arr, sd.ctypes.data, len(params))
+        if not self._h:
+            raise MTGPError(lib().mtgp_last_error(), "mtgp_batch_create")
+        self.params = list(params)
+        self.count = len(params)
+
+    @staticmethod
+    def _reqs(requests: Iterable):
+        reqs = list(requests)
+        arr = (RequestC * max(1, len(reqs)))()
+        for i, (gen, kind, n, out) in enumerate(reqs):
+            ptr = out.data_ptr() if isinstance(out, torch.Tensor) else int(out)
+            arr[i].gen, arr[i].kind, arr[i].n, arr[i].out = gen, kind, n, ptr
+        return arr, len(reqs)
+
+    def generate(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
+        """requests: iterable of (gen, kind, n, out tensor or device address)."""
+        arr, k = self._reqs(requests)
+        _check(lib().mtgp_batch_generate(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate")
+
+    def generate_plain(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
+        arr, k = self._reqs(requests)
+        _check(lib().mtgp_batch_generate_plain(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate_plain")
+
+    def set_launch(self, mode: int = -1, threads: int = 0, spl: int = 1, lds_words: int = 0, grid: int = 0):
+        """Override the persistent launch shape (mode -1 restores the automatic choice)."""
+        _check(lib().mtgp_batch_set_launch(self._h, mode, threads, spl, lds_words, grid), "mtgp_batch_set_launch")
+
+    def get_state(self, gen: int):
+        import numpy as np
+        words = np.zeros(state_words(self.params[gen].mexp), dtype=np.uint32)
+        consumed = ctypes.c_uint64(0)
+        _check(lib().mtgp_batch_get_state(self._h, gen, words.ctypes.data, ctypes.byref(consumed)),
+               "mtgp_batch_get_state")
+        return words, consumed.value
+
+    def set_state(self, gen: int, words, consumed: int = 0):
+        import numpy as np
+        w = np.ascontiguousarray(np.asarray(words, dtype=np.uint32))
+        _check(lib().mtgp_batch_set_state(self._h, gen, w.ctypes.data, consumed), "mtgp_batch_set_state")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mtgp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

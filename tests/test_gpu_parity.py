@@ -1,0 +1,205 @@
+"""Bit-exact parity of the HIP path (through the C ABI) against the oracle.
+
+Every output kind is compared bit for bit; integer-valued work has no
+tolerance. Inputs are the seeded synthetic parameter sets of
+paper_1005_4973_amd.inputs.
+"""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1005_4973_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+KINDS = (I.KIND_U32, I.KIND_F12, I.KIND_F01)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1005_4973_amd import mtgp
+    mtgp.lib()
+    return mtgp
+
+
+def host_bits(t):
+    import torch
+    return t.view(torch.int32).cpu().numpy().view(np.uint32)
+
+
+def oracle_out(ps, seed, n, kind):
+    out, st = O.stream(ps, seed, n, kind)
+    return out, st
+
+
+def pool():
+    return ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4))
+
+
+# ---------------------------------------------------------------------------
+
+def test_single_stream_all_kinds(M):
+    (ps,), n = I.single_stream()
+    say(f"single_stream M={ps.pos} n={n}")
+    for kind in KINDS:
+        g = M.Generator(ps, 1234)
+        out = g.generate(n, kind)
+        words, consumed = g.get_state()
+        ref, st = oracle_out(ps, 1234, n, kind)
+        np.testing.assert_array_equal(host_bits(out), ref)
+        np.testing.assert_array_equal(words, st)
+        assert consumed == n
+        g.close()
+
+
+@pytest.mark.parametrize("mexp", [89, 107, 521, 2203, 11213, 23209, 44497])
+def test_m_sweep_and_ragged_lengths(M, mexp):
+    N = O.nwords(mexp)
+    Ms = sorted({2, 3, N // 2, N - 3, N - 2, N - 1} & set(range(2, N)))
+    base = I.draw_param_set(mexp, I.SplitMix64(mexp + 1), I.M_POLICY_FULL)
+    for m in Ms:
+        ps = I.ParamSet(mexp, m, base.sh1, base.sh2, base.param_tbl, base.temper_tbl)
+        W = N - m
+        lengths = sorted({1, 2, N - 1, N, N + 1, W - 1 if W > 1 else 1, W, W + 1, 2 * W + 3,
+                          3 * N + 7, 5000})
+        say(f"mexp={mexp} M={m} lengths={lengths}")
+        for kind in KINDS:
+            g = M.Generator(ps, 77)
+            st = O.seed_state(77, mexp)
+            for n in lengths:
+                out = g.generate(n, kind)
+                ref = O.generate(ps, st, n, kind)
+                np.testing.assert_array_equal(host_bits(out), ref, err_msg=f"M={m} n={n} kind={kind}")
+            words, _ = g.get_state()
+            np.testing.assert_array_equal(words, st)
+            g.close()
+
+
+def test_continuation_mixed_kinds(M):
+    (ps,), _ = I.single_stream()
+    g = M.Generator(ps, 5)
+    st = O.seed_state(5, ps.mexp)
+    rng = I.SplitMix64(11)
+    for i in range(30):
+        n = rng.uniform_int(0, 3000)
+        kind = KINDS[i % 3]
+        out = g.generate(n, kind) if n > 0 else None
+        ref = O.generate(ps, st, n, kind)
+        if n > 0:
+            np.testing.assert_array_equal(host_bits(out), ref)
+    words, consumed = g.get_state()
+    np.testing.assert_array_equal(words, st)
+
+
+def test_set_state_and_linearity(M):
+    (ps,), _ = I.single_stream()
+    N = O.nwords(ps.mexp)
+    s1 = I.random_state(N, 1)
+    s2 = I.random_state(N, 2)
+    outs = []
+    for s in (s1, s2, s1 ^ s2):
+        g = M.Generator(ps, 0)
+        g.set_state(s, 0)
+        outs.append(host_bits(g.generate(4 * N + 5)))
+        ref = O.generate(ps, s.copy(), 4 * N + 5)
+        np.testing.assert_array_equal(outs[-1], ref)
+        g.close()
+    np.testing.assert_array_equal(outs[2], outs[0] ^ outs[1])
+
+
+def test_fullperiod_sets(M):
+    import json
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fullperiod_sets.json")))
+    for e in d["sets"]:
+        ps = I.ParamSet(e["mexp"], e["pos"], e["sh1"], e["sh2"], tuple(e["param_tbl"]), tuple(e["temper_tbl"]))
+        g = M.Generator(ps, 3)
+        out = g.generate(20000)
+        ref, _ = O.stream(ps, 3, 20000)
+        np.testing.assert_array_equal(host_bits(out), ref)
+        g.close()
+
+
+def test_error_paths(M):
+    import torch
+    (ps,), _ = I.single_stream()
+    g = M.Generator(ps, 1)
+    buf = torch.empty(16, dtype=torch.int32, device="cuda")
+    # misaligned output pointer
+    rc = M.lib().mtgp_generate_uint32(g._h, 4, M.ctypes.c_void_p(buf.data_ptr() + 2), None)
+    assert rc == M.MTGP_EINVAL
+    # NULL output with n > 0
+    assert M.lib().mtgp_generate_uint32(g._h, 4, None, None) == M.MTGP_EINVAL
+    # n = 0 with NULL output is a no-op
+    assert M.lib().mtgp_generate_uint32(g._h, 0, None, None) == M.MTGP_OK
+    _, consumed = g.get_state()
+    assert consumed == 0
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+
+def check_batch_against_oracle(M, params, seeds, calls, plain=False):
+    """calls: list of request lists [(gen, kind, n)]; outputs checked after each call."""
+    import torch
+    b = M.Batch(params, seeds)
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    for reqs in calls:
+        bufs = [torch.empty(max(n, 1), dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+        rq = [(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)]
+        (b.generate_plain if plain else b.generate)(rq)
+        torch.cuda.synchronize()
+        with pool() as ex:
+            refs = list(ex.map(lambda r: O.generate(params[r[0]], states[r[0]], r[2], r[1]), reqs))
+        for (g, k, n), buf, ref in zip(reqs, bufs, refs):
+            np.testing.assert_array_equal(host_bits(buf)[:n], ref, err_msg=f"gen={g} kind={k} n={n}")
+    for g in range(len(params)):
+        words, _ = b.get_state(g)
+        np.testing.assert_array_equal(words, states[g], err_msg=f"state gen={g}")
+    b.close()
+
+
+def test_batch_small_uneven_mixed(M):
+    params, reqs = I.batched_uneven(count=64, seed=77, log2_lo=0, log2_hi=15)
+    seeds = I.state_seeds(len(params))
+    calls = [[(r.gen, r.kind, r.n) for r in reqs],
+             [(r.gen, (r.kind + 1) % 3, r.n // 3 + 1) for r in reqs[::2]]]
+    say("batch small uneven")
+    check_batch_against_oracle(M, params, seeds, calls)
+    check_batch_against_oracle(M, params, seeds, calls, plain=True)
+
+
+def test_batch_independent_128_all_kinds(M):
+    """128 MTGP-11213 generators, 2^22 outputs each, in one launch, per kind."""
+    params, n = I.independent_128()
+    seeds = I.state_seeds(len(params))
+    say("independent_128 full size")
+    calls = [[(g, kind, n) for g in range(len(params))] for kind in KINDS]
+    check_batch_against_oracle(M, params, seeds, calls)
+
+
+def test_batch_rejects_bad_requests(M):
+    import torch
+    params, _ = I.independent_128()
+    b = M.Batch(params[:4], I.state_seeds(4))
+    buf = torch.empty(64, dtype=torch.int32, device="cuda")
+    with pytest.raises(M.MTGPError):
+        b.generate([(0, 0, 8, buf), (0, 0, 8, buf)])          # same generator twice
+    with pytest.raises(M.MTGPError):
+        b.generate([(9, 0, 8, buf)])                          # no such generator
+    with pytest.raises(M.MTGPError):
+        b.generate([(1, 3, 8, buf)])                          # no such kind
+    b.close()
