@@ -153,16 +153,33 @@ uint32_t mtgp_batch_size(const mtgp_batch_t *b);
 void mtgp_batch_destroy(mtgp_batch_t *b);
 
 /* ---------------------------------------------------------------------------
+ * Plans: a fixed request list for repeated replay. Creation validates the
+ * requests, orders them longest critical path first, uploads the list once
+ * and captures the persistent launch into a HIP graph. Each mtgp_plan_launch
+ * continues every listed generator by its request's n outputs, written to
+ * the same output buffers. The batch must outlive its plans; plan launches
+ * and other calls on the same batch must be stream-ordered. Returns NULL on
+ * error (see mtgp_last_error()).
+ * ------------------------------------------------------------------------- */
+typedef struct mtgp_plan mtgp_plan_t;
+mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq);
+int mtgp_plan_launch(mtgp_plan_t *p, void *stream);
+void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's last stream */
+
+/* ---------------------------------------------------------------------------
  * Launch shape (for tuning; results are identical for every valid shape).
- *   mode 0: one workgroup of `threads` lanes per generator, `spl` steps per
- *           lane per round (spl in {1, 2, 4}), a barrier between rounds.
+ *   mode 0: one workgroup of `threads` lanes per generator, a barrier between
+ *           rounds; steps per lane per round up to `spl` (1, 2 or 4).
  *   mode 1: one wavefront per generator, `threads`/64 wavefronts per
- *           workgroup, spl in {1, 2, 4, 6, 8, 12, 16}, no barriers.
- * A round computes W = min(N - M, lanes * spl) steps (section 3.2), lanes =
- * threads (mode 0) or 64 (mode 1). lds_words is the LDS window per generator
- * (0 = automatic; must be >= 2N + W for every generator served) and grid the
- * number of workgroups (0 = automatic). mode < 0 restores the automatic
- * choice. Returns MTGP_EINVAL for an unsupported shape.
+ *           workgroup, no barriers; spl up to 1, 2, 4, 6, 8, 12 or 16.
+ * Each generator uses the largest supported s <= spl with lanes*s <= N - M
+ * (lanes = threads in mode 0, 64 in mode 1), so a round computes
+ * W = min(N - M, lanes*s) steps (section 3.2). lds_words is the LDS window per
+ * generator (0 = automatic; must be >= 2N + lanes*s for every generator
+ * served) and grid the number of workgroups (0 = automatic). mode < 0
+ * restores the automatic choice. Returns MTGP_EINVAL for an unsupported
+ * shape; a batch call whose requests do not fit the shape fails with
+ * MTGP_EINVAL.
  * ------------------------------------------------------------------------- */
 int mtgp_batch_set_launch(mtgp_batch_t *b, int mode, int threads, int spl, int lds_words, int grid);
 int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words);

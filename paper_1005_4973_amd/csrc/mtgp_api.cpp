@@ -1,7 +1,7 @@
 // C ABI of the MTGP library (declared in include/mtgp.h): parameter
 // validation, state seeding, device residency of states and parameters, and
 // the launch paths (single generator, persistent batch, one launch per
-// request).
+// request, graph-captured plans).
 #include "../../include/mtgp.h"
 #include "mtgp_internal.h"
 
@@ -24,10 +24,14 @@ int fail(int code)
     return code;
 }
 
-constexpr uint32_t kMinMexp = 65;       // N >= 3
-constexpr uint32_t kMaxMexp = 65536;    // N <= 2048
-constexpr int kMaxLdsWords = 16384 - 64;  // default window: 64 KiB per workgroup incl. tables
+constexpr uint32_t kMinMexp = 65;           // N >= 3
+constexpr uint32_t kMaxMexp = 65536;        // N <= 2048
 constexpr size_t kLdsPerCu = 160u * 1024u;  // gfx950 LDS per compute unit
+constexpr size_t kUnitLdsExtra = 64;        // table words ahead of each window
+constexpr uint32_t kWavesPerCu = 32;        // resident wavefront limit per CU used for sizing grids
+// A window this large (in words) takes more than half of a CU's LDS, so the
+// hardware places at most one such workgroup per CU.
+constexpr uint32_t kExclusiveWindow = 24000;
 
 uint32_t words_of(uint32_t mexp) { return (mexp + 31u) / 32u; }
 
@@ -85,57 +89,6 @@ void seed_words(uint32_t seed, uint32_t n, uint32_t *x)
     }
 }
 
-// Launch shape for one generator alone on the GPU: one workgroup with as
-// many lanes as the round width N - M allows (up to 1024, two steps per lane
-// beyond that) and the largest LDS window.
-LaunchShape single_shape(uint32_t N, uint32_t M)
-{
-    LaunchShape s;
-    s.mode = kModeGroup;
-    const uint32_t wfull = N - M;
-    s.spl = wfull <= 1024 ? 1 : 2;
-    uint32_t lanes = (wfull + s.spl - 1) / s.spl;
-    lanes = (lanes + 63u) / 64u * 64u;
-    s.threads = (int)std::min<uint32_t>(1024u, std::max<uint32_t>(64u, lanes));
-    s.lds_words = kMaxLdsWords;
-    s.grid = 1;
-    return s;
-}
-
-bool spl_supported(int mode, int spl)
-{
-    if (mode == kModeGroup)
-        return spl == 1 || spl == 2 || spl == 4;
-    return spl == 1 || spl == 2 || spl == 4 || spl == 6 || spl == 8 || spl == 12 || spl == 16;
-}
-
-// LDS bytes a launch shape asks for per workgroup.
-size_t shape_lds_bytes(const LaunchShape &s)
-{
-    const size_t per = (size_t)(64 + s.lds_words) * 4;
-    return s.mode == kModeGroup ? per : per * (size_t)(s.threads / 64);
-}
-
-// Largest LDS window the items of a launch need: 2N + lanes*spl words each.
-uint32_t window_need(const std::vector<GenRecord> &recs, const std::vector<uint32_t> &gens, const LaunchShape &s)
-{
-    uint32_t need = 0;
-    for (uint32_t g : gens)
-        need = std::max<uint32_t>(need, 2 * recs[g].N + round_span(s));
-    return need;
-}
-
-bool shape_valid(const LaunchShape &s, size_t max_lds)
-{
-    if (s.mode != kModeGroup && s.mode != kModeWave)
-        return false;
-    if (s.threads < 64 || s.threads > 1024 || s.threads % 64 != 0)
-        return false;
-    if (!spl_supported(s.mode, s.spl) || s.lds_words <= 0 || s.grid <= 0)
-        return false;
-    return shape_lds_bytes(s) <= max_lds;
-}
-
 int check_out(const void *out, size_t n)
 {
     if (n == 0)
@@ -145,8 +98,8 @@ int check_out(const void *out, size_t n)
     return MTGP_OK;
 }
 
-// Largest dynamic LDS a workgroup may use on the current device; kernels are
-// opted in to it once per process.
+// Largest dynamic LDS a workgroup may use on the current device; the kernels
+// are opted in to it once per process.
 size_t device_max_lds()
 {
     static size_t cached = 0;
@@ -162,12 +115,70 @@ size_t device_max_lds()
                  val > 0)
             lim = (size_t)val;
     }
-    if (lim > kLdsPerCu)
-        lim = kLdsPerCu;
+    lim = std::min(lim, kLdsPerCu);
     if (lim > 65536 && opt_in_lds(lim) != hipSuccess)
         lim = 65536;
     cached = lim;
     return cached;
+}
+
+bool spl_supported(int mode, int spl)
+{
+    if (mode == kModeGroup)
+        return spl == 1 || spl == 2 || spl == 4;
+    return spl == 1 || spl == 2 || spl == 4 || spl == 6 || spl == 8 || spl == 12 || spl == 16;
+}
+
+uint32_t shape_units(const LaunchShape &s) { return s.mode == kModeGroup ? 1u : (uint32_t)(s.threads / 64); }
+
+// LDS bytes a launch shape asks for per workgroup.
+size_t shape_lds_bytes(const LaunchShape &s)
+{
+    return (size_t)shape_units(s) * (kUnitLdsExtra + (size_t)s.lds_words) * 4u;
+}
+
+uint32_t max_window_words(const LaunchShape &s, size_t max_lds)
+{
+    return (uint32_t)(max_lds / 4u / shape_units(s) - kUnitLdsExtra);
+}
+
+// Window a generator needs under a shape: 2N + lanes * item_spl words.
+uint32_t window_need(const GenRecord &r, const LaunchShape &s) { return 2 * r.N + round_span(r.N, r.M, s); }
+
+bool shape_valid(const LaunchShape &s, size_t max_lds)
+{
+    if (s.mode != kModeGroup && s.mode != kModeWave)
+        return false;
+    if (s.threads < 64 || s.threads > 1024 || s.threads % 64 != 0)
+        return false;
+    if (!spl_supported(s.mode, s.spl) || s.lds_words <= 0 || s.grid <= 0)
+        return false;
+    return shape_lds_bytes(s) <= max_lds;
+}
+
+// Workgroups that fit on the device at once for a shape (LDS and wave limits).
+uint64_t resident_groups(const LaunchShape &s, int cu_count)
+{
+    const size_t by_lds = std::max<size_t>(1u, kLdsPerCu / shape_lds_bytes(s));
+    const size_t by_waves = std::max<size_t>(1u, kWavesPerCu / (size_t)(s.threads / 64));
+    return (uint64_t)cu_count * std::min(by_lds, by_waves);
+}
+
+// Launch shape for one generator alone on the GPU: one workgroup of 256
+// lanes (fewer when N - M < 256), up to four steps per lane, and the largest
+// LDS window (fewest compactions).
+LaunchShape single_shape(const GenRecord &r, size_t max_lds)
+{
+    LaunchShape s;
+    s.mode = kModeGroup;
+    const uint32_t w = r.N - r.M;
+    const uint32_t lanes = w >= 256 ? 256u : (w + 63u) / 64u * 64u;
+    s.threads = (int)std::max<uint32_t>(64u, lanes);
+    s.spl = 4;
+    s.grid = 1;
+    s.lds_words = 1;
+    s.lds_words = (int)max_window_words(s, max_lds);
+    return s;
 }
 
 }  // namespace
@@ -201,6 +212,159 @@ struct mtgp_batch {
     bool have_override = false;
     LaunchShape override_shape;
 };
+
+struct mtgp_plan {
+    mtgp_batch *b = nullptr;
+    std::vector<WorkItem> items;
+    WorkItem *d_items = nullptr;
+    uint32_t *d_counters = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    LaunchShape shape;
+};
+
+namespace {
+
+// Default persistent launch shape for a batch (when no override is set):
+// - at most as many requests as CUs: one 256-lane workgroup per generator
+//   and one workgroup per CU (an exclusive LDS window), because each
+//   generator's rounds are latency-bound and two workgroups on one CU would
+//   share its issue slots;
+// - more requests: 256-lane workgroups with the smallest window that fits
+//   every request, so several generators share each CU.
+LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem> &items)
+{
+    LaunchShape s;
+    s.mode = kModeGroup;
+    s.threads = 256;
+    s.spl = 4;
+    s.grid = 1;
+    uint32_t need = 0;
+    for (const WorkItem &it : items)
+        need = std::max(need, window_need(b->recs[it.gen], s));
+    s.lds_words = 1;
+    const uint32_t cap = max_window_words(s, b->max_lds);
+    if (items.size() <= (size_t)b->cu_count)
+        s.lds_words = (int)std::min(cap, std::max(need, kExclusiveWindow));
+    else
+        s.lds_words = (int)std::min(cap, std::max(need, 4096u));
+    s.grid = (int)std::min<uint64_t>(items.size(), resident_groups(s, b->cu_count));
+    return s;
+}
+
+// Resolve the launch shape for a set of items: override (with automatic
+// window and grid filled in) or default; validated against every item.
+int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, LaunchShape &out)
+{
+    LaunchShape s;
+    if (b->have_override) {
+        s = b->override_shape;
+        if (s.lds_words == 0) {
+            uint32_t need = 0;
+            for (const WorkItem &it : items)
+                need = std::max(need, window_need(b->recs[it.gen], s));
+            s.lds_words = (int)need;
+        }
+        if (s.grid == 0) {
+            const uint64_t units = shape_units(s);
+            const uint64_t want = (items.size() + units - 1) / units;
+            s.grid = (int)std::min<uint64_t>(want, resident_groups(s, b->cu_count));
+        }
+    } else {
+        s = batch_default_shape(b, items);
+    }
+    if (!shape_valid(s, b->max_lds))
+        return MTGP_EINVAL;
+    for (const WorkItem &it : items)
+        if ((uint32_t)s.lds_words < window_need(b->recs[it.gen], s))
+            return MTGP_EINVAL;
+    out = s;
+    return MTGP_OK;
+}
+
+int validate_requests(const mtgp_batch *b, const mtgp_request *reqs, uint32_t nreq, bool unique)
+{
+    if (!b || (nreq > 0 && !reqs))
+        return MTGP_EINVAL;
+    std::vector<uint8_t> seen(unique ? b->count : 0, 0);
+    for (uint32_t i = 0; i < nreq; i++) {
+        const mtgp_request &r = reqs[i];
+        if (r.gen >= b->count || r.kind > 2 || check_out(r.out, r.n) != MTGP_OK)
+            return MTGP_EINVAL;
+        if (unique && r.n > 0) {
+            if (seen[r.gen])
+                return MTGP_EINVAL;
+            seen[r.gen] = 1;
+        }
+    }
+    return MTGP_OK;
+}
+
+std::vector<WorkItem> items_of(const mtgp_request *reqs, uint32_t nreq)
+{
+    std::vector<WorkItem> items;
+    items.reserve(nreq);
+    for (uint32_t i = 0; i < nreq; i++) {
+        if (reqs[i].n == 0)
+            continue;
+        WorkItem it;
+        std::memset(&it, 0, sizeof(it));
+        it.out = reinterpret_cast<uint64_t>(reqs[i].out);
+        it.n = reqs[i].n;
+        it.gen = reqs[i].gen;
+        it.kind = (uint16_t)reqs[i].kind;
+        items.push_back(it);
+    }
+    return items;
+}
+
+// Fill in steps per lane and order the items longest critical path first
+// (rounds = ceil(n / W), each round weighted by its slots per lane).
+void finish_items(const mtgp_batch *b, std::vector<WorkItem> &items, const LaunchShape &s)
+{
+    for (WorkItem &it : items)
+        it.spl = item_spl(b->recs[it.gen].N, b->recs[it.gen].M, s);
+    auto cost = [&](const WorkItem &it) {
+        const GenRecord &r = b->recs[it.gen];
+        const uint64_t w = round_width(r.N, r.M, s);
+        return (it.n + w - 1) / w * (uint64_t)it.spl;
+    };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const WorkItem &x, const WorkItem &y) { return cost(x) > cost(y); });
+}
+
+void batch_free(mtgp_batch *b)
+{
+    if (!b)
+        return;
+    hipFree(b->d_recs);
+    hipFree(b->d_states);
+    hipFree(b->d_counters);
+    hipFree(b->d_items);
+    if (b->h_items)
+        hipHostFree(b->h_items);
+    if (b->items_free)
+        hipEventDestroy(b->items_free);
+    delete b;
+}
+
+void plan_free(mtgp_plan *p)
+{
+    if (!p)
+        return;
+    if (p->exec)
+        hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        hipGraphDestroy(p->graph);
+    if (p->capture)
+        hipStreamDestroy(p->capture);
+    hipFree(p->d_items);
+    hipFree(p->d_counters);
+    delete p;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -256,8 +420,8 @@ mtgp_t *mtgp_create(const mtgp_param_set *ps, uint32_t seed)
         fail(MTGP_EDEVICE);
         return nullptr;
     }
-    g->shape = single_shape(N, g->rec.M);
     g->max_lds = device_max_lds();
+    g->shape = single_shape(g->rec, g->max_lds);
     return g;
 }
 
@@ -275,9 +439,9 @@ static int generate_kind(mtgp_t *g, size_t n, void *out, void *stream, uint32_t 
     it.out = reinterpret_cast<uint64_t>(out);
     it.n = n;
     it.gen = 0;
-    it.kind = kind;
-    hipError_t e = launch_generate(g->d_rec, g->d_state, nullptr, 1, nullptr, it, g->shape, s);
-    if (e != hipSuccess)
+    it.kind = (uint16_t)kind;
+    it.spl = item_spl(g->rec.N, g->rec.M, g->shape);
+    if (launch_generate(g->d_rec, g->d_state, nullptr, 1, nullptr, it, g->shape, s) != hipSuccess)
         return fail(MTGP_EDEVICE);
     g->consumed += n;
     g->last = s;
@@ -332,24 +496,32 @@ int mtgp_set_state(mtgp_t *g, const uint32_t *host_words, uint64_t consumed)
     return MTGP_OK;
 }
 
+int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words)
+{
+    if (!g)
+        return fail(MTGP_EINVAL);
+    if (mode < 0) {
+        g->shape = single_shape(g->rec, g->max_lds);
+        return MTGP_OK;
+    }
+    LaunchShape s;
+    s.mode = mode;
+    s.threads = mode == kModeGroup ? threads : 64;
+    s.spl = spl;
+    s.grid = 1;
+    s.lds_words = 1;
+    if (!shape_valid(s, g->max_lds) || lds_words < 0)
+        return fail(MTGP_EINVAL);
+    s.lds_words = lds_words > 0 ? lds_words : (int)max_window_words(s, g->max_lds);
+    if (!shape_valid(s, g->max_lds) || (uint32_t)s.lds_words < window_need(g->rec, s))
+        return fail(MTGP_EINVAL);
+    g->shape = s;
+    return MTGP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Batches
 // ---------------------------------------------------------------------------
-
-static void batch_free(mtgp_batch *b)
-{
-    if (!b)
-        return;
-    hipFree(b->d_recs);
-    hipFree(b->d_states);
-    hipFree(b->d_counters);
-    hipFree(b->d_items);
-    if (b->h_items)
-        hipHostFree(b->h_items);
-    if (b->items_free)
-        hipEventDestroy(b->items_free);
-    delete b;
-}
 
 mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds, uint32_t count)
 {
@@ -415,89 +587,18 @@ void mtgp_batch_destroy(mtgp_batch_t *b)
     batch_free(b);
 }
 
-static int validate_requests(mtgp_batch *b, const mtgp_request *reqs, uint32_t nreq, bool unique)
-{
-    if (!b || (nreq > 0 && !reqs))
-        return MTGP_EINVAL;
-    std::vector<uint8_t> seen(unique ? b->count : 0, 0);
-    for (uint32_t i = 0; i < nreq; i++) {
-        const mtgp_request &r = reqs[i];
-        if (r.gen >= b->count || r.kind > 2 || check_out(r.out, r.n) != MTGP_OK)
-            return MTGP_EINVAL;
-        if (unique && r.n > 0) {
-            if (seen[r.gen])
-                return MTGP_EINVAL;
-            seen[r.gen] = 1;
-        }
-    }
-    return MTGP_OK;
-}
-
-// Default persistent launch shape for a batch: 256-lane workgroups, up to two
-// steps per lane (round width up to 512), an LDS window that holds the
-// largest state twice plus a round, and as many resident workgroups as fit.
-static LaunchShape batch_shape(mtgp_batch *b, const std::vector<uint32_t> &gens)
-{
-    LaunchShape s;
-    s.mode = kModeGroup;
-    s.threads = 256;
-    s.spl = 2;
-    s.grid = 1;
-    const uint32_t need = window_need(b->recs, gens, s);
-    uint32_t L = std::max<uint32_t>(need, 4096u);
-    s.lds_words = (int)L;
-    const size_t lds_bytes = shape_lds_bytes(s);
-    const size_t by_lds = std::max<size_t>(1u, kLdsPerCu / lds_bytes);
-    const size_t by_waves = 32u / (size_t)(s.threads / 64);
-    const size_t per_cu = std::min(by_lds, by_waves);
-    s.grid = (int)std::min<uint64_t>(gens.size(), (uint64_t)b->cu_count * per_cu);
-    return s;
-}
-
 int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream)
 {
     if (validate_requests(b, reqs, nreq, true) != MTGP_OK)
         return fail(MTGP_EINVAL);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<WorkItem> items;
-    items.reserve(nreq);
-    for (uint32_t i = 0; i < nreq; i++) {
-        if (reqs[i].n == 0)
-            continue;
-        WorkItem it;
-        std::memset(&it, 0, sizeof(it));
-        it.out = reinterpret_cast<uint64_t>(reqs[i].out);
-        it.n = reqs[i].n;
-        it.gen = reqs[i].gen;
-        it.kind = reqs[i].kind;
-        items.push_back(it);
-    }
+    std::vector<WorkItem> items = items_of(reqs, nreq);
     if (items.empty())
         return MTGP_OK;
-    std::vector<uint32_t> gens;
-    gens.reserve(items.size());
-    for (const WorkItem &it : items)
-        gens.push_back(it.gen);
-    LaunchShape shape = b->have_override ? b->override_shape : batch_shape(b, gens);
-    if (b->have_override) {
-        if (shape.lds_words == 0)
-            shape.lds_words = (int)window_need(b->recs, gens, shape);
-        if (shape.grid == 0) {
-            const size_t by_lds = std::max<size_t>(1u, kLdsPerCu / shape_lds_bytes(shape));
-            const size_t by_waves = 32u / (size_t)(shape.threads / 64);
-            const size_t units = shape.mode == kModeGroup ? 1 : (size_t)(shape.threads / 64);
-            const uint64_t want = (items.size() + units - 1) / units;
-            shape.grid = (int)std::min<uint64_t>(want, (uint64_t)b->cu_count * std::min(by_lds, by_waves));
-        }
-    }
-    if (!shape_valid(shape, b->max_lds) || (uint32_t)shape.lds_words < window_need(b->recs, gens, shape))
+    LaunchShape shape;
+    if (resolve_shape(b, items, shape) != MTGP_OK)
         return fail(MTGP_EINVAL);
-    // longest critical path first: rounds = ceil(n / W)
-    std::stable_sort(items.begin(), items.end(), [&](const WorkItem &x, const WorkItem &y) {
-        const uint64_t wx = round_width(b->recs[x.gen].N, b->recs[x.gen].M, shape);
-        const uint64_t wy = round_width(b->recs[y.gen].N, b->recs[y.gen].M, shape);
-        return (x.n + wx - 1) / wx > (y.n + wy - 1) / wy;
-    });
+    finish_items(b, items, shape);
     const uint32_t nitems = (uint32_t)items.size();
     if (b->items_pending) {
         if (hipEventSynchronize(b->items_free) != hipSuccess)
@@ -543,13 +644,14 @@ int mtgp_batch_generate_plain(mtgp_batch_t *b, const mtgp_request *reqs, uint32_
         if (r.n == 0)
             continue;
         const GenRecord &rec = b->recs[r.gen];
+        const LaunchShape shape = single_shape(rec, b->max_lds);
         WorkItem it;
         std::memset(&it, 0, sizeof(it));
         it.out = reinterpret_cast<uint64_t>(r.out);
         it.n = r.n;
         it.gen = r.gen;
-        it.kind = r.kind;
-        const LaunchShape shape = single_shape(rec.N, rec.M);
+        it.kind = (uint16_t)r.kind;
+        it.spl = item_spl(rec.N, rec.M, shape);
         if (launch_generate(b->d_recs, b->d_states, nullptr, 1, nullptr, it, shape, s) != hipSuccess)
             return fail(MTGP_EDEVICE);
         b->consumed[r.gen] += r.n;
@@ -581,27 +683,6 @@ int mtgp_batch_set_launch(mtgp_batch_t *b, int mode, int threads, int spl, int l
     return MTGP_OK;
 }
 
-int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words)
-{
-    if (!g)
-        return fail(MTGP_EINVAL);
-    if (mode < 0) {
-        g->shape = single_shape(g->rec.N, g->rec.M);
-        return MTGP_OK;
-    }
-    LaunchShape s;
-    s.mode = mode;
-    s.threads = mode == kModeGroup ? threads : 64;
-    s.spl = spl;
-    s.grid = 1;
-    s.lds_words = lds_words > 0 ? lds_words : kMaxLdsWords;
-    const uint32_t need = 2 * g->rec.N + round_span(s);
-    if (!shape_valid(s, g->max_lds) || (uint32_t)s.lds_words < need)
-        return fail(MTGP_EINVAL);
-    g->shape = s;
-    return MTGP_OK;
-}
-
 int mtgp_batch_get_state(mtgp_batch_t *b, uint32_t gen, uint32_t *host_words, uint64_t *consumed)
 {
     if (!b || gen >= b->count || !host_words)
@@ -625,6 +706,85 @@ int mtgp_batch_set_state(mtgp_batch_t *b, uint32_t gen, const uint32_t *host_wor
         return fail(MTGP_EDEVICE);
     b->consumed[gen] = consumed;
     return MTGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plans: a fixed request list, uploaded once, its persistent launch captured
+// in a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+
+mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq)
+{
+    if (validate_requests(b, reqs, nreq, true) != MTGP_OK) {
+        fail(MTGP_EINVAL);
+        return nullptr;
+    }
+    mtgp_plan *p = new (std::nothrow) mtgp_plan();
+    if (!p) {
+        fail(MTGP_ENOMEM);
+        return nullptr;
+    }
+    p->b = b;
+    p->items = items_of(reqs, nreq);
+    if (p->items.empty() || resolve_shape(b, p->items, p->shape) != MTGP_OK) {
+        delete p;
+        fail(MTGP_EINVAL);
+        return nullptr;
+    }
+    finish_items(b, p->items, p->shape);
+    const uint32_t nitems = (uint32_t)p->items.size();
+    if (hipMalloc(&p->d_items, nitems * sizeof(WorkItem)) != hipSuccess ||
+        hipMalloc(&p->d_counters, 2 * sizeof(uint32_t)) != hipSuccess) {
+        plan_free(p);
+        fail(MTGP_ENOMEM);
+        return nullptr;
+    }
+    if (hipMemcpy(p->d_items, p->items.data(), nitems * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(p->d_counters, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
+        plan_free(p);
+        fail(MTGP_EDEVICE);
+        return nullptr;
+    }
+    WorkItem none;
+    std::memset(&none, 0, sizeof(none));
+    bool ok = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        const hipError_t le = launch_generate(b->d_recs, b->d_states, p->d_items, nitems, p->d_counters, none,
+                                              p->shape, p->capture);
+        const hipError_t ce = hipStreamEndCapture(p->capture, &p->graph);
+        ok = le == hipSuccess && ce == hipSuccess && p->graph != nullptr;
+    }
+    if (ok)
+        ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+        plan_free(p);
+        fail(MTGP_EDEVICE);
+        return nullptr;
+    }
+    return p;
+}
+
+int mtgp_plan_launch(mtgp_plan_t *p, void *stream)
+{
+    if (!p)
+        return fail(MTGP_EINVAL);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipGraphLaunch(p->exec, s) != hipSuccess)
+        return fail(MTGP_EDEVICE);
+    for (const WorkItem &it : p->items)
+        p->b->consumed[it.gen] += it.n;
+    p->b->last = s;
+    return MTGP_OK;
+}
+
+void mtgp_plan_destroy(mtgp_plan_t *p)
+{
+    if (!p)
+        return;
+    if (p->b)
+        hipStreamSynchronize(p->b->last);
+    plan_free(p);
 }
 
 }  // extern "C"

@@ -111,205 +111,183 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const uin
     }
 }
 
-template <int KIND, int SPL>
+// Rounds of one stream. All full rounds (cnt = W) run in runs between two
+// compactions of the window, each run a tight 32-bit loop; the last,
+// partial round (n mod W steps) follows. Loop control is scalar and
+// per-round scalar work is kept to a few instructions, because in the group
+// form every wavefront repeats it. WAVE: one wavefront, no barriers (LDS
+// operations of a wavefront complete in order).
+template <int KIND, int SPL, bool WAVE>
 __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const uint32_t *__restrict__ rec,
                                            const uint32_t *__restrict__ otb, uint32_t N, uint32_t M,
                                            uint32_t sh1, uint32_t sh2, uint32_t mask, uint32_t W,
                                            uint32_t L, uint64_t n, gu32 *__restrict__ out,
-                                           uint32_t *__restrict__ state)
+                                           uint32_t *__restrict__ state, uint32_t lane, uint32_t T)
 {
-    const uint32_t t = threadIdx.x;
-    const uint32_t T = blockDim.x;
     const uint32_t span = T * SPL;   // slots written per round
+    uint64_t full = n / W;
+    const uint32_t rem = (uint32_t)(n - full * W);
     uint32_t base = 0;
-    uint64_t i0 = 0;
-    while (i0 < n) {
-        const uint64_t left = n - i0;
-        const uint32_t cnt = left < W ? (uint32_t)left : W;
+    gu32 *ob = out;
+    while (full > 0) {
         if (base + N + span > L) {
             // base > L - N - span >= N: source and destination are disjoint
-            for (uint32_t k = t; k < N; k += T)
+            for (uint32_t k = lane; k < N; k += T)
                 X[k] = X[base + k];
-            __syncthreads();
+            if (!WAVE)
+                __syncthreads();
             base = 0;
         }
-        round_steps<KIND, SPL>(X + base, rec, otb, N, M, sh1, sh2, mask, t, T, cnt, out + i0);
-        __syncthreads();
-        base += cnt;
-        i0 += cnt;
+        // rounds that fit before the window must be compacted again
+        const uint32_t room = (L - N - span - base) / W + 1;
+        const uint32_t k = full < room ? (uint32_t)full : room;
+        for (uint32_t j = 0; j < k; ++j) {
+            round_steps<KIND, SPL>(X + base, rec, otb, N, M, sh1, sh2, mask, lane, T, W, ob);
+            if (!WAVE)
+                __syncthreads();
+            base += W;
+            ob += W;
+        }
+        full -= k;
+    }
+    if (rem > 0) {
+        if (base + N + span > L) {
+            for (uint32_t k = lane; k < N; k += T)
+                X[k] = X[base + k];
+            if (!WAVE)
+                __syncthreads();
+            base = 0;
+        }
+        round_steps<KIND, SPL>(X + base, rec, otb, N, M, sh1, sh2, mask, lane, T, rem, ob);
+        if (!WAVE)
+            __syncthreads();
+        base += rem;
     }
     // x_n .. x_{n+N-1} back to HBM (section 8: the next call continues)
-    for (uint32_t k = t; k < N; k += T)
+    for (uint32_t k = lane; k < N; k += T)
         state[k] = X[base + k];
 }
 
-template <int SPL>
-__global__ __launch_bounds__(1024) void mtgp_generate_kernel(const GenRecord *__restrict__ recs,
-                                                             uint32_t *__restrict__ states,
-                                                             const WorkItem *__restrict__ items,
-                                                             uint32_t nitems, uint32_t *counters,
-                                                             WorkItem single, uint32_t L)
-{
-    extern __shared__ uint32_t smem[];
-    uint32_t *rec = smem;
-    uint32_t *otb = smem + 16;
-    uint32_t *slot = smem + 32;
-    uint32_t *X = smem + kTableWords;
-    const uint32_t t = threadIdx.x;
-    const uint32_t T = blockDim.x;
-
-    for (uint32_t iter = 0;; ++iter) {
-        WorkItem it;
-        if (items == nullptr) {                 // one item passed by value, grid of 1
-            if (iter > 0)
-                break;
-            it = single;
-        } else if (counters == nullptr) {       // item i in workgroup i
-            if (iter > 0 || blockIdx.x >= nitems)
-                break;
-            it = items[blockIdx.x];
-        } else {                                // persistent: pop from the queue
-            if (t == 0)
-                slot[0] = atomicAdd(&counters[0], 1u);
-            __syncthreads();
-            const uint32_t q = __builtin_amdgcn_readfirstlane(slot[0]);
-            __syncthreads();
-            if (q >= nitems)
-                break;
-            it = items[q];
-        }
-        const uint32_t gen = __builtin_amdgcn_readfirstlane(it.gen);
-        const uint32_t kind = __builtin_amdgcn_readfirstlane(it.kind);
-        const GenRecord &g = recs[gen];
-        const uint32_t N = g.N, M = g.M;
-        uint32_t *state = states + g.state_off;
-        const uint32_t W = (N - M) < T * SPL ? (N - M) : T * SPL;
-
-        for (uint32_t k = t; k < N; k += T)
-            X[k] = state[k];
-        if (t < 16) {
-            rec[t] = g.rec[t];
-            otb[t] = kind == 0 ? g.tmp[t] : g.flt[t];
-        }
-        __syncthreads();
-
-        gu32 *out = reinterpret_cast<gu32 *>(it.out);
-        if (kind == 0)
-            run_stream<0, SPL>(X, rec, otb, N, M, g.sh1, g.sh2, g.mask, W, L, it.n, out, state);
-        else if (kind == 1)
-            run_stream<1, SPL>(X, rec, otb, N, M, g.sh1, g.sh2, g.mask, W, L, it.n, out, state);
-        else
-            run_stream<2, SPL>(X, rec, otb, N, M, g.sh1, g.sh2, g.mask, W, L, it.n, out, state);
-        __syncthreads();   // the next item overwrites the window and tables
-    }
-
-    if (items != nullptr && counters != nullptr && t == 0) {
-        __threadfence();
-        const uint32_t done = atomicAdd(&counters[1], 1u);
-        if (done == gridDim.x - 1) {    // every pop has returned: reset for the next launch
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Wave form: each wavefront of the workgroup serves its own generator. The
-// 64 lanes take steps k = lane + 64c (c < SPL) of each round. LDS operations
-// of one wavefront complete in issue order, so a round's reads see the
-// previous round's writes without a barrier or an LDS wait; the SPL
-// independent steps per lane hide the LDS latency instead.
-// LDS per wavefront: [0,16) recursion table, [16,32) output table, then the
-// window X of L words.
+// The generation kernel. Two forms share the round code:
+//   group (WAVE = false): the whole workgroup serves one generator; T lanes
+//       take steps k = lane + c*T (c < spl) of each round, with a barrier
+//       between rounds.
+//   wave  (WAVE = true): each wavefront serves its own generator with its own
+//       LDS window; steps k = lane + 64c. LDS operations of one wavefront
+//       complete in issue order, so a round's reads see the previous round's
+//       writes without a barrier or an LDS wait; the spl independent steps
+//       per lane hide the LDS latency instead.
+// Work comes from one item passed by value (grid of one), from item i for
+// unit i, or -- persistent form -- from a queue in `counters`, in the order
+// the host sorted the items (longest critical path first).
+// LDS per unit: [0,16) recursion table, [16,32) output table, [32] queue
+// slot, then the window X of L words.
 // ---------------------------------------------------------------------------
 
-template <int KIND, int SPL>
-__device__ __forceinline__ void run_stream_wave(uint32_t *__restrict__ X, const uint32_t *__restrict__ rec,
-                                                const uint32_t *__restrict__ otb, uint32_t N, uint32_t M,
-                                                uint32_t sh1, uint32_t sh2, uint32_t mask, uint32_t W,
-                                                uint32_t L, uint64_t n, gu32 *__restrict__ out,
-                                                uint32_t *__restrict__ state, uint32_t lane)
+template <int KIND, bool WAVE>
+__device__ __forceinline__ void run_item(uint32_t spl, uint32_t *X, const uint32_t *rec, const uint32_t *otb,
+                                         const GenRecord &g, uint32_t W, uint32_t L, uint64_t n, gu32 *out,
+                                         uint32_t *state, uint32_t lane, uint32_t T)
 {
-    constexpr uint32_t span = 64u * SPL;
-    uint32_t base = 0;
-    uint64_t i0 = 0;
-    while (i0 < n) {
-        const uint64_t left = n - i0;
-        const uint32_t cnt = left < W ? (uint32_t)left : W;
-        if (base + N + span > L) {
-            for (uint32_t k = lane; k < N; k += 64)
-                X[k] = X[base + k];
-            base = 0;
+#define MTGP_RUN(S) \
+    run_stream<KIND, S, WAVE>(X, rec, otb, g.N, g.M, g.sh1, g.sh2, g.mask, W, L, n, out, state, lane, T)
+    if (WAVE) {
+        switch (spl) {
+        case 1: MTGP_RUN(1); break;
+        case 2: MTGP_RUN(2); break;
+        case 4: MTGP_RUN(4); break;
+        case 6: MTGP_RUN(6); break;
+        case 8: MTGP_RUN(8); break;
+        case 12: MTGP_RUN(12); break;
+        default: MTGP_RUN(16); break;
         }
-        round_steps<KIND, SPL>(X + base, rec, otb, N, M, sh1, sh2, mask, lane, 64u, cnt, out + i0);
-        base += cnt;
-        i0 += cnt;
+    } else {
+        switch (spl) {
+        case 1: MTGP_RUN(1); break;
+        case 2: MTGP_RUN(2); break;
+        default: MTGP_RUN(4); break;
+        }
     }
-    for (uint32_t k = lane; k < N; k += 64)
-        state[k] = X[base + k];
+#undef MTGP_RUN
 }
 
-template <int SPL>
-__global__ __launch_bounds__(1024) void mtgp_wave_kernel(const GenRecord *__restrict__ recs,
-                                                         uint32_t *__restrict__ states,
-                                                         const WorkItem *__restrict__ items,
-                                                         uint32_t nitems, uint32_t *counters,
-                                                         WorkItem single, uint32_t L)
+template <bool WAVE>
+__global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict__ recs, uint32_t *__restrict__ states,
+                                                    const WorkItem *__restrict__ items, uint32_t nitems,
+                                                    uint32_t *counters, WorkItem single, uint32_t L)
 {
     extern __shared__ uint32_t smem[];
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t waves = blockDim.x >> 6;
-    uint32_t *rec = smem + wave * (kTableWords + L);
+    const uint32_t lane = WAVE ? (threadIdx.x & 63u) : threadIdx.x;
+    const uint32_t T = WAVE ? 64u : blockDim.x;
+    const uint32_t unit = WAVE ? (threadIdx.x >> 6) : 0u;
+    const uint32_t units = WAVE ? (blockDim.x >> 6) : 1u;
+    uint32_t *rec = smem + unit * (kTableWords + L);
     uint32_t *otb = rec + 16;
+    uint32_t *slot = rec + 32;
     uint32_t *X = rec + kTableWords;
 
     for (uint32_t iter = 0;; ++iter) {
         WorkItem it;
-        if (items == nullptr) {                 // one item passed by value, one wavefront
-            if (iter > 0 || blockIdx.x > 0 || wave > 0)
+        if (items == nullptr) {                 // one item passed by value, one unit
+            if (iter > 0 || blockIdx.x > 0 || unit > 0)
                 break;
             it = single;
-        } else if (counters == nullptr) {       // item i in wavefront i
-            const uint32_t w = blockIdx.x * waves + wave;
+        } else if (counters == nullptr) {       // item i in unit i
+            const uint32_t w = blockIdx.x * units + unit;
             if (iter > 0 || w >= nitems)
                 break;
             it = items[w];
-        } else {                                // persistent: each wavefront pops its own item
-            uint32_t q = 0;
-            if (lane == 0)
-                q = atomicAdd(&counters[0], 1u);
-            q = __builtin_amdgcn_readfirstlane(q);
+        } else {                                // persistent: pop from the queue
+            uint32_t q;
+            if (WAVE) {
+                q = 0;
+                if (lane == 0)
+                    q = atomicAdd(&counters[0], 1u);
+                q = __builtin_amdgcn_readfirstlane(q);
+            } else {
+                if (lane == 0)
+                    slot[0] = atomicAdd(&counters[0], 1u);
+                __syncthreads();
+                q = __builtin_amdgcn_readfirstlane(slot[0]);
+                __syncthreads();
+            }
             if (q >= nitems)
                 break;
             it = items[q];
         }
         const uint32_t gen = __builtin_amdgcn_readfirstlane(it.gen);
-        const uint32_t kind = __builtin_amdgcn_readfirstlane(it.kind);
+        const uint32_t kind = __builtin_amdgcn_readfirstlane((uint32_t)it.kind);
+        const uint32_t spl = __builtin_amdgcn_readfirstlane((uint32_t)it.spl);
         const GenRecord &g = recs[gen];
         const uint32_t N = g.N, M = g.M;
         uint32_t *state = states + g.state_off;
-        const uint32_t W = (N - M) < 64u * SPL ? (N - M) : 64u * SPL;
+        const uint32_t W = (N - M) < T * spl ? (N - M) : T * spl;
 
-        for (uint32_t k = lane; k < N; k += 64)
+        for (uint32_t k = lane; k < N; k += T)
             X[k] = state[k];
         if (lane < 16) {
             rec[lane] = g.rec[lane];
             otb[lane] = kind == 0 ? g.tmp[lane] : g.flt[lane];
         }
+        if (!WAVE)
+            __syncthreads();
+
         gu32 *out = reinterpret_cast<gu32 *>(it.out);
         if (kind == 0)
-            run_stream_wave<0, SPL>(X, rec, otb, N, M, g.sh1, g.sh2, g.mask, W, L, it.n, out, state, lane);
+            run_item<0, WAVE>(spl, X, rec, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == 1)
-            run_stream_wave<1, SPL>(X, rec, otb, N, M, g.sh1, g.sh2, g.mask, W, L, it.n, out, state, lane);
+            run_item<1, WAVE>(spl, X, rec, otb, g, W, L, it.n, out, state, lane, T);
         else
-            run_stream_wave<2, SPL>(X, rec, otb, N, M, g.sh1, g.sh2, g.mask, W, L, it.n, out, state, lane);
+            run_item<2, WAVE>(spl, X, rec, otb, g, W, L, it.n, out, state, lane, T);
+        if (!WAVE)
+            __syncthreads();   // the next item overwrites the window and tables
     }
 
     if (items != nullptr && counters != nullptr && lane == 0) {
         __threadfence();
         const uint32_t done = atomicAdd(&counters[1], 1u);
-        if (done == gridDim.x * waves - 1) {    // every pop has returned: reset for the next launch
+        if (done == gridDim.x * units - 1) {    // every pop has returned: reset for the next launch
             atomicExch(&counters[0], 0u);
             atomicExch(&counters[1], 0u);
         }
@@ -322,56 +300,25 @@ hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkIt
 {
     const dim3 grid(shape.grid), block(shape.threads);
     const uint32_t L = (uint32_t)shape.lds_words;
-    if (shape.mode == kModeGroup) {
-        const size_t lds = (size_t)(kTableWords + L) * sizeof(uint32_t);
-#define MTGP_LAUNCH_GROUP(S)                                                                          \
-    hipLaunchKernelGGL(mtgp_generate_kernel<S>, grid, block, lds, stream, recs, states, items, nitems, \
-                       counters, single, L)
-        switch (shape.spl) {
-        case 1: MTGP_LAUNCH_GROUP(1); break;
-        case 2: MTGP_LAUNCH_GROUP(2); break;
-        case 4: MTGP_LAUNCH_GROUP(4); break;
-        default: return hipErrorInvalidValue;
-        }
-#undef MTGP_LAUNCH_GROUP
-    } else {
-        const size_t lds = (size_t)(shape.threads / 64) * (kTableWords + L) * sizeof(uint32_t);
-#define MTGP_LAUNCH_WAVE(S)                                                                           \
-    hipLaunchKernelGGL(mtgp_wave_kernel<S>, grid, block, lds, stream, recs, states, items, nitems,     \
-                       counters, single, L)
-        switch (shape.spl) {
-        case 1: MTGP_LAUNCH_WAVE(1); break;
-        case 2: MTGP_LAUNCH_WAVE(2); break;
-        case 4: MTGP_LAUNCH_WAVE(4); break;
-        case 6: MTGP_LAUNCH_WAVE(6); break;
-        case 8: MTGP_LAUNCH_WAVE(8); break;
-        case 12: MTGP_LAUNCH_WAVE(12); break;
-        case 16: MTGP_LAUNCH_WAVE(16); break;
-        default: return hipErrorInvalidValue;
-        }
-#undef MTGP_LAUNCH_WAVE
-    }
+    const uint32_t units = shape.mode == kModeGroup ? 1u : (uint32_t)(shape.threads / 64);
+    const size_t lds = (size_t)units * (kTableWords + L) * sizeof(uint32_t);
+    if (shape.mode == kModeGroup)
+        hipLaunchKernelGGL(mtgp_kernel<false>, grid, block, lds, stream, recs, states, items, nitems, counters,
+                           single, L);
+    else
+        hipLaunchKernelGGL(mtgp_kernel<true>, grid, block, lds, stream, recs, states, items, nitems, counters,
+                           single, L);
     return hipGetLastError();
 }
 
 hipError_t opt_in_lds(size_t bytes)
 {
     const int b = (int)bytes;
-    hipError_t e = hipSuccess;
-#define MTGP_OPT_IN(K)                                                                            \
-    if (e == hipSuccess)                                                                          \
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&K), hipFuncAttributeMaxDynamicSharedMemorySize, b)
-    MTGP_OPT_IN(mtgp_generate_kernel<1>);
-    MTGP_OPT_IN(mtgp_generate_kernel<2>);
-    MTGP_OPT_IN(mtgp_generate_kernel<4>);
-    MTGP_OPT_IN(mtgp_wave_kernel<1>);
-    MTGP_OPT_IN(mtgp_wave_kernel<2>);
-    MTGP_OPT_IN(mtgp_wave_kernel<4>);
-    MTGP_OPT_IN(mtgp_wave_kernel<6>);
-    MTGP_OPT_IN(mtgp_wave_kernel<8>);
-    MTGP_OPT_IN(mtgp_wave_kernel<12>);
-    MTGP_OPT_IN(mtgp_wave_kernel<16>);
-#undef MTGP_OPT_IN
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mtgp_kernel<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mtgp_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return e;
 }
 

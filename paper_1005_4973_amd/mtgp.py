@@ -59,6 +59,9 @@ _SIGNATURES = {
     "mtgp_batch_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64]),
     "mtgp_batch_size": (ctypes.c_uint32, [ctypes.c_void_p]),
     "mtgp_batch_destroy": (None, [ctypes.c_void_p]),
+    "mtgp_batch_plan_create": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32]),
+    "mtgp_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_plan_destroy": (None, [ctypes.c_void_p]),
     "mtgp_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 5),
     "mtgp_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 4),
     "mtgp_last_error": (ctypes.c_int, []),
@@ -215,6 +218,10 @@ class Batch:
         arr, k = self._reqs(requests)
         _check(lib().mtgp_batch_generate_plain(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate_plain")
 
+    def plan(self, requests: Iterable) -> "Plan":
+        """Capture the persistent launch for a fixed request list (see Plan)."""
+        return Plan(self, requests)
+
     def set_launch(self, mode: int = -1, threads: int = 0, spl: int = 1, lds_words: int = 0, grid: int = 0):
         """Override the persistent launch shape (mode -1 restores the automatic choice)."""
         _check(lib().mtgp_batch_set_launch(self._h, mode, threads, spl, lds_words, grid), "mtgp_batch_set_launch")
@@ -235,6 +242,32 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             lib().mtgp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A fixed request list whose persistent launch is captured in a HIP graph
+    (mtgp_batch_plan_create); each launch() continues every listed stream."""
+
+    def __init__(self, batch: Batch, requests: Iterable):
+        arr, k = Batch._reqs(requests)
+        self.batch = batch
+        self._h = lib().mtgp_batch_plan_create(batch._h, arr, k)
+        if not self._h:
+            raise MTGPError(lib().mtgp_last_error(), "mtgp_batch_plan_create")
+
+    def launch(self, stream: Optional[torch.cuda.Stream] = None):
+        _check(lib().mtgp_plan_launch(self._h, _stream_ptr(stream)), "mtgp_plan_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mtgp_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -203,3 +203,88 @@ def test_batch_rejects_bad_requests(M):
     with pytest.raises(M.MTGPError):
         b.generate([(1, 3, 8, buf)])                          # no such kind
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# Launch shapes: every valid shape gives the same bits
+# ---------------------------------------------------------------------------
+
+SHAPES = [
+    (0, 64, 1, 0, 0), (0, 64, 4, 0, 0), (0, 256, 1, 0, 0), (0, 256, 4, 0, 0), (0, 512, 2, 0, 0),
+    (0, 1024, 1, 0, 0), (0, 256, 4, 24000, 0), (1, 64, 1, 0, 0), (1, 64, 4, 0, 0), (1, 256, 6, 0, 0),
+    (1, 128, 16, 0, 0), (1, 256, 8, 4096, 3),
+]
+
+
+def test_launch_shapes_parity(M):
+    import torch
+    params = (I.draw_param_sets([11213] * 4, 61, I.M_POLICY_WIDE) + I.draw_param_sets([23209] * 2, 62)
+              + I.draw_param_sets([44497] * 2, 63) + I.draw_param_sets([89, 521, 2203], 64, I.M_POLICY_FULL))
+    seeds = I.state_seeds(len(params))
+    b = M.Batch(params, seeds)
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    rng = I.SplitMix64(99)
+    for sh in SHAPES:
+        say(f"shape {sh}")
+        b.set_launch(*sh)
+        reqs = [(g, g % 3, rng.uniform_int(1, 9000)) for g in range(len(params))]
+        bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+        b.generate([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+        torch.cuda.synchronize()
+        for (g, k, n), buf in zip(reqs, bufs):
+            ref = O.generate(params[g], states[g], n, k)
+            np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"shape={sh} gen={g}")
+    b.set_launch(-1)
+    for g in range(len(params)):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g])
+    b.close()
+
+
+def test_single_generator_shapes(M):
+    (ps,), _ = I.single_stream()
+    st = O.seed_state(21, ps.mexp)
+    g = M.Generator(ps, 21)
+    for sh in [(0, 64, 4, 0), (0, 256, 1, 0), (0, 1024, 1, 2000), (1, 64, 16, 0), (1, 64, 4, 1000), (-1, 0, 1, 0)]:
+        g.set_launch(*sh)
+        out = g.generate(7777, I.KIND_F01)
+        np.testing.assert_array_equal(host_bits(out), O.generate(ps, st, 7777, I.KIND_F01), err_msg=str(sh))
+    with pytest.raises(M.MTGPError):
+        g.set_launch(0, 256, 1, 100)          # window smaller than 2N + W
+    with pytest.raises(M.MTGPError):
+        g.set_launch(0, 96, 1, 0)             # not a multiple of 64
+    with pytest.raises(M.MTGPError):
+        g.set_launch(1, 64, 5, 0)             # unsupported steps per lane
+    g.close()
+
+
+def test_plan_graph_replays(M):
+    """A captured plan replayed several times, with eager work and syncs in
+    between, continues every stream exactly."""
+    import torch
+    params, reqs0 = I.batched_uneven(count=16, seed=31, log2_lo=4, log2_hi=14)
+    seeds = I.state_seeds(len(params))
+    b = M.Batch(params, seeds)
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    planned = [r for r in reqs0 if r.gen < 12]
+    bufs = {r.gen: torch.empty(r.n, dtype=torch.int32, device="cuda") for r in planned}
+    plan = b.plan([(r.gen, r.kind, r.n, bufs[r.gen]) for r in planned])
+    eager_gens = [12, 13, 14, 15]
+    for rep in range(4):
+        say(f"plan replay {rep}")
+        plan.launch()
+        torch.cuda.synchronize()
+        for r in planned:
+            ref = O.generate(params[r.gen], states[r.gen], r.n, r.kind)
+            np.testing.assert_array_equal(host_bits(bufs[r.gen]), ref, err_msg=f"replay={rep} gen={r.gen}")
+        # eager work on other generators between replays
+        eb = [torch.empty(500 + rep, dtype=torch.int32, device="cuda") for _ in eager_gens]
+        b.generate([(g, 0, 500 + rep, t) for g, t in zip(eager_gens, eb)])
+        torch.cuda.synchronize()
+        for g, t in zip(eager_gens, eb):
+            np.testing.assert_array_equal(host_bits(t), O.generate(params[g], states[g], 500 + rep, 0))
+        _ = (torch.arange(1000, device="cuda") * 3).sum().item()
+    for g in range(len(params)):
+        w, consumed = b.get_state(g)
+        np.testing.assert_array_equal(w, states[g])
+    plan.close()
+    b.close()
