@@ -1,17 +1,29 @@
 """Throughput benchmark of the MTGP HIP path on one MI355X.
 
-One step = the whole generation path for the 128-generator workload: 128
-distinct MTGP-11213 generators (paper M rule), 2^22 outputs each, generated
-as uint32, then float32 in [1,2), then float32 in [0,1) -- one persistent
-batched launch per output kind, each writing 2 GiB. Every launch loads each
+Headline step (`value`): the 128-generator workload -- 128 distinct
+MTGP-11213 generators (M drawn by the paper's thread-count rule), 2^22
+outputs each, generated as uint32, then float32 in [1,2), then float32 in
+[0,1): three persistent batched launches (one per output kind), each a
+replay of a HIP-graph-captured plan writing 2 GiB. Every launch loads each
 state into LDS, runs the recursion rounds with tempering and conversion,
 stores outputs with nontemporal writes, and stores the states back.
 
-Prints one JSON line. `value` is numbers/s (all kinds count) with the inputs
-(states, parameters) resident in HBM when the timed region starts.
+The same JSON line also reports:
+  batched_uneven  4096 generators (2:1:1 over p = 11213, 23209, 44497),
+                  lengths log-uniform in [2^10, 2^24], mixed kinds: one
+                  graph-captured persistent launch vs one launch per request
+  large_states    256 generators at p = 23209 and at p = 44497, 2^24 uint32 each
+  single_stream   one MTGP-11213 generator, 2^20 uint32
+  serving         65536 resident MTGP-11213 states, Poisson arrivals at a swept
+                  fraction of the measured saturation rate, log-normal sizes
+                  (median 2^16, sigma 1.5, clipped to [2^10, 2^26]):
+                  p50/p99 latency and sustained numbers/s
+`value` is numbers/s with states and parameters resident in HBM when the
+timed region starts.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -20,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SECTIONS = ("batched_uneven", "large_states", "single_stream", "serving")
 
 
 def parse():
@@ -29,20 +42,34 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (default: host cores, max 16)")
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="comma-separated extra sections to run (empty for the headline only)")
     return ap.parse_args()
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def gbs(nbytes, seconds):
+    return nbytes / seconds / 1e9
+
+
+def roof(nbytes, seconds):
+    a = gbs(nbytes, seconds)
+    return {"GBs": round(a, 1), "frac_of_8TBs": round(a / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(params, n_per_gen, kinds, threads):
-    """The oracle on the host cores: one generator per task, a bounded sample."""
+    """The oracle on the host cores: one generator and kind per task."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     from paper_1005_4973_amd import inputs as I
 
     # about 15 s of single-core oracle work: every generator, every kind,
     # three times the per-generator length of one step
-    sample_gens = len(params)
     n = 3 * n_per_gen
-    tasks = [(g, k) for g in range(sample_gens) for k in kinds]
+    tasks = [(g, k) for g in range(len(params)) for k in kinds]
 
     def run(task):
         g, k = task
@@ -54,9 +81,171 @@ def cpu_baseline(params, n_per_gen, kinds, threads):
     with ThreadPoolExecutor(max_workers=threads) as ex:
         total = sum(ex.map(run, tasks))
     dt = time.perf_counter() - t0
-    return {"value": total / dt / 1e9, "unit": "G numbers/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample_gens} generators x {n} outputs x {len(kinds)} kinds "
+    return {"value": round(total / dt / 1e9, 4), "unit": "G numbers/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(params)} generators x {n} outputs x {len(kinds)} kinds "
                       f"({total} numbers, {dt:.2f} s wall)"}
+
+
+def timed_ms(torch, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    best = math.inf
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+# ---------------------------------------------------------------------------
+# headline: 128 independent generators
+# ---------------------------------------------------------------------------
+
+def headline(args, torch, I, mtgp):
+    params, n = I.independent_128()
+    G = len(params)
+    kinds = (I.KIND_U32, I.KIND_F12, I.KIND_F01)
+    batch = mtgp.Batch(params, I.state_seeds(G))
+    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+    plans = [batch.plan([(g, k, n, out.data_ptr() + 4 * g * n) for g in range(G)]) for k in kinds]
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        for p in plans:
+            p.launch(stream)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps * len(kinds))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    i = 0
+    for _ in range(args.steps):
+        for p in plans:
+            ev[i][0].record(stream)
+            p.launch(stream)
+            ev[i][1].record(stream)
+            i += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    numbers_per_step = G * n * len(kinds)
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+    N = 351
+    # algorithmic bytes of one launch: outputs + state in and out + parameter record
+    alg_bytes = G * (4 * n + 8 * N + 256)
+    achieved = alg_bytes / avg_launch_s / 1e9
+    for p in plans:
+        p.close()
+    batch.close()
+    del out
+    torch.cuda.empty_cache()
+    return params, n, kinds, {
+        "value": round(numbers_per_step * args.steps / dt / 1e9, 3),
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "mtgp_kernel<false> (workgroup per generator)",
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+
+
+# ---------------------------------------------------------------------------
+# extra sections
+# ---------------------------------------------------------------------------
+
+def batched_uneven(torch, I, mtgp):
+    params, reqs = I.batched_uneven()
+    G = len(params)
+    tot = sum(r.n for r in reqs)
+    batch = mtgp.Batch(params, I.state_seeds(G))
+    out = torch.empty(tot, dtype=torch.int32, device="cuda")
+    base = out.data_ptr()
+    rq = [(r.gen, r.kind, r.n, base + 4 * r.offset) for r in reqs]
+    plan = batch.plan(rq)
+    ms_b = timed_ms(torch, lambda: plan.launch(), reps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.generate_plain(rq)
+    torch.cuda.synchronize()
+    ms_p = (time.perf_counter() - t0) * 1e3
+    plan.close()
+    batch.close()
+    del out
+    torch.cuda.empty_cache()
+    Ns = {11213: 351, 23209: 726, 44497: 1391}
+    alg = sum(4 * r.n + 8 * Ns[params[r.gen].mexp] + 256 for r in reqs)
+    return {"generators": G, "numbers": tot,
+            "batched": {"ms": round(ms_b, 3), "G_numbers_s": round(tot / ms_b / 1e6, 2), **roof(alg, ms_b / 1e3)},
+            "plain_one_launch_per_request": {"ms": round(ms_p, 1), "G_numbers_s": round(tot / ms_p / 1e6, 3)},
+            "speedup_batched_vs_plain": round(ms_p / ms_b, 1)}
+
+
+def large_states(torch, I, mtgp):
+    res = {}
+    for mexp, N in ((23209, 726), (44497, 1391)):
+        params, n = I.large_states(mexp)
+        G = len(params)
+        batch = mtgp.Batch(params, I.state_seeds(G))
+        out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+        plan = batch.plan([(g, 0, n, out.data_ptr() + 4 * g * n) for g in range(G)])
+        ms = timed_ms(torch, lambda: plan.launch(), reps=3)
+        plan.close()
+        batch.close()
+        del out
+        torch.cuda.empty_cache()
+        alg = G * (4 * n + 8 * N + 256)
+        res[f"p{mexp}"] = {"generators": G, "numbers": G * n, "ms": round(ms, 3),
+                           "G_numbers_s": round(G * n / ms / 1e6, 2), **roof(alg, ms / 1e3)}
+    return res
+
+
+def single_stream(torch, I, mtgp):
+    (ps,), n = I.single_stream()
+    g = mtgp.Generator(ps, 1234)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    ms = timed_ms(torch, lambda: g.generate(n, I.KIND_U32, out=out), reps=5)
+    g.close()
+    return {"M": ps.pos, "numbers": n, "ms": round(ms, 4), "G_numbers_s": round(n / ms / 1e6, 3)}
+
+
+def serving(torch, I, mtgp):
+    from paper_1005_4973_amd import serve
+    G = 65536
+    params = I.serving_params(G)
+    batch = mtgp.Batch(params, I.state_seeds(G))
+
+    def run(trace, realtime):
+        srv = serve.Server(serve.GpuExecutor(batch), mem_budget_bytes=8 << 30, chunk=1 << 18, depth=2,
+                           keep_outputs=False)
+        return srv.run(trace, realtime=realtime)
+
+    # saturation: every request available at once
+    sat_trace = I.serving_trace(3000, rate_per_s=1.0, num_gens=G, seed=5001)
+    run(sat_trace[:300], False)          # warm-up
+    st = run(sat_trace, False)
+    sat_rate = st.completed / st.wall_s
+    points = [{"load": "saturation", "req_per_s": round(sat_rate, 1),
+               "numbers_per_s": round(st.numbers / st.wall_s, 1),
+               "p50_ms": round(st.percentile(50) * 1e3, 3), "p99_ms": round(st.percentile(99) * 1e3, 3)}]
+    for frac in (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+        lam = frac * sat_rate
+        num = int(min(12000, max(300, lam * 1.5)))
+        trace = I.serving_trace(num, rate_per_s=lam, num_gens=G, seed=6000 + int(frac * 100))
+        s = run(trace, True)
+        points.append({"load": frac, "req_per_s": round(lam, 1), "requests": num, "completed": s.completed,
+                       "numbers_per_s": round(s.numbers / s.wall_s, 1),
+                       "p50_ms": round(s.percentile(50) * 1e3, 3), "p99_ms": round(s.percentile(99) * 1e3, 3)})
+        log(f"serving load {frac}: {points[-1]}")
+    batch.close()
+    torch.cuda.empty_cache()
+    return {"generators": G, "chunk": 1 << 18, "mem_budget_GiB": 8, "sigma": 1.5, "points": points}
 
 
 def main():
@@ -71,49 +260,17 @@ def main():
     from paper_1005_4973_amd import mtgp
 
     torch.cuda.set_device(0)
-    params, n = I.independent_128()
-    G = len(params)
-    kinds = (I.KIND_U32, I.KIND_F12, I.KIND_F01)
-    batch = mtgp.Batch(params, I.state_seeds(G))
-    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
-    reqs = [[(g, k, n, out.data_ptr() + 4 * g * n) for g in range(G)] for k in kinds]
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        for r in reqs:
-            batch.generate(r, stream)
-    torch.cuda.synchronize()
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps * len(kinds))]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    i = 0
-    for _ in range(args.steps):
-        for r in reqs:
-            ev[i][0].record(stream)
-            batch.generate(r, stream)
-            ev[i][1].record(stream)
-            i += 1
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    numbers_per_step = G * n * len(kinds)
-    value = numbers_per_step * args.steps / dt
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
-    avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
-    N = 351
-    alg_bytes = sum(4 * n + 8 * N + 256 for _ in range(G))   # outputs + state in/out + parameters
-    achieved = alg_bytes / avg_launch_s / 1e9
+    params, n, kinds, head = headline(args, torch, I, mtgp)
+    log(f"headline: {head['value']} G numbers/s")
 
     res = {
         "metric": "G numbers/s (uint32 and float32 outputs) and % of HBM write roofline",
-        "value": round(value / 1e9, 3),
+        "value": head["value"],
         "unit": "G numbers/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -121,17 +278,22 @@ def main():
         "data": "synthetic (seeded parameter sets and states)",
         "config": {"workload": "128 independent MTGP-11213 generators (distinct seeded parameter sets, "
                                "M in [2,95]), 2^22 outputs each as uint32, float32 [1,2) and float32 [0,1); "
-                               "one persistent batched launch per output kind",
-                   "generators": G, "mexp": 11213, "outputs_per_generator": n,
+                               "one graph-captured persistent launch per output kind",
+                   "generators": 128, "mexp": 11213, "outputs_per_generator": n,
                    "kinds": ["uint32", "float32_1to2", "float32_0to1"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "mtgp_generate_kernel", "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
+        "roofline": head["roofline"],
     }
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
         res["cpu_baseline"] = cpu_baseline(params, n, kinds, threads)
-    batch.close()
+        log(f"cpu baseline: {res['cpu_baseline']['value']} G numbers/s")
+    sections = [s for s in args.sections.split(",") if s]
+    fns = {"batched_uneven": batched_uneven, "large_states": large_states, "single_stream": single_stream,
+           "serving": serving}
+    for name in sections:
+        t0 = time.perf_counter()
+        res[name] = fns[name](torch, I, mtgp)
+        log(f"{name}: done in {time.perf_counter() - t0:.1f} s: {json.dumps(res[name])[:300]}")
     print(json.dumps(res), flush=True)
 
 

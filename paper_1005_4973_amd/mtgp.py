@@ -42,6 +42,16 @@ class RequestC(ctypes.Structure):
                 ("n", ctypes.c_uint64), ("out", ctypes.c_void_p)]
 
 
+def _request_dtype():
+    import numpy as np
+    return np.dtype({"names": ["gen", "kind", "n", "out"],
+                     "formats": [np.uint32, np.uint32, np.uint64, np.uint64],
+                     "offsets": [RequestC.gen.offset, RequestC.kind.offset, RequestC.n.offset, RequestC.out.offset],
+                     "itemsize": ctypes.sizeof(RequestC)})
+
+
+REQUEST_DTYPE = _request_dtype()
+
 # Every symbol the header declares, with its ctypes signature.
 _SIGNATURES = {
     "mtgp_state_words": (ctypes.c_uint32, [ctypes.c_uint32]),
@@ -213,6 +223,20 @@ class Batch:
         """requests: iterable of (gen, kind, n, out tensor or device address)."""
         arr, k = self._reqs(requests)
         _check(lib().mtgp_batch_generate(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate")
+
+    def generate_arrays(self, gens, kinds, ns, ptrs, stream: Optional[torch.cuda.Stream] = None):
+        """Same as generate, with the requests as equal-length integer arrays
+        (generator, kind, n, output device address): no per-request Python work."""
+        import numpy as np
+        k = len(gens)
+        arr = np.zeros(k, dtype=REQUEST_DTYPE)
+        arr["gen"] = gens
+        arr["kind"] = kinds
+        arr["n"] = ns
+        arr["out"] = ptrs
+        rc = lib().mtgp_batch_generate(self._h, ctypes.cast(arr.ctypes.data, ctypes.POINTER(RequestC)), k,
+                                       _stream_ptr(stream))
+        _check(rc, "mtgp_batch_generate")
 
     def generate_plain(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
         arr, k = self._reqs(requests)

@@ -1,0 +1,253 @@
+"""Continuous-batching request loop over resident MTGP states.
+
+Requests (generator, kind, n) arrive over time. The server keeps every
+generator state resident in HBM (one mtgp batch), admits requests in arrival
+order while their output footprint (4n bytes) fits a memory budget, and runs
+ticks: each tick advances every admitted request by up to `chunk` outputs in
+one persistent batched launch, so small requests finish while large ones are
+still streaming and requests that arrive mid-run join at the next tick.
+Requests for one generator are served strictly in arrival order (one chunk
+per tick, from the oldest unfinished request of that generator), so each
+result is exactly the stream segment it would get alone.
+
+Up to `depth` ticks are queued on the device at once (stream order keeps
+consecutive chunks of one generator in sequence); completion is detected with
+events and a request's latency is its completion time minus its arrival time.
+
+The executor interface (launch / ready / wait) lets tests drive the same
+scheduler with a CPU executor.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
+
+
+@dataclass
+class Request:
+    rid: int
+    gen: int
+    kind: int
+    n: int
+    arrival: float                  # seconds, on the server clock
+    out: object = None              # output buffer (executor-specific)
+    done: int = 0                   # outputs already scheduled
+    finished: int = 0               # outputs completed on the device
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    rejected: bool = False
+
+    @property
+    def nbytes(self) -> int:
+        return 4 * self.n
+
+
+class Executor:
+    """Runs one tick: a list of (gen, kind, n, out, offset) chunks."""
+
+    def alloc(self, req: Request):
+        raise NotImplementedError
+
+    def free(self, req: Request):
+        pass
+
+    def launch(self, chunks: List[Tuple[int, int, int, object, int]]):
+        raise NotImplementedError
+
+    def ready(self, handle) -> bool:
+        raise NotImplementedError
+
+    def wait(self, handle):
+        raise NotImplementedError
+
+
+class GpuExecutor(Executor):
+    """Chunks go to one mtgp batch launch on a dedicated stream; an event per tick."""
+
+    def __init__(self, batch, stream=None):
+        import torch
+        self.torch = torch
+        self.batch = batch
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+
+    def alloc(self, req: Request):
+        t = self.torch
+        dtype = t.int32 if req.kind == 0 else t.float32
+        with t.cuda.stream(self.stream):
+            req.out = t.empty(req.n, dtype=dtype, device="cuda")
+
+    def free(self, req: Request):
+        pass   # the caller owns req.out; torch frees it when dropped
+
+    def launch(self, chunks):
+        import numpy as np
+        t = self.torch
+        k = len(chunks)
+        gens = np.fromiter((c[0] for c in chunks), dtype=np.uint32, count=k)
+        kinds = np.fromiter((c[1] for c in chunks), dtype=np.uint32, count=k)
+        ns = np.fromiter((c[2] for c in chunks), dtype=np.uint64, count=k)
+        ptrs = np.fromiter((c[3].data_ptr() + 4 * c[4] for c in chunks), dtype=np.uint64, count=k)
+        self.batch.generate_arrays(gens, kinds, ns, ptrs, self.stream)
+        ev = t.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    def ready(self, handle) -> bool:
+        return handle.query()
+
+    def wait(self, handle):
+        handle.synchronize()
+
+
+@dataclass
+class ServeStats:
+    offered_rate: float
+    completed: int
+    rejected: int
+    numbers: int
+    wall_s: float
+    latencies: List[float] = field(default_factory=list)
+
+    def percentile(self, q: float) -> float:
+        if not self.latencies:
+            return math.nan
+        xs = sorted(self.latencies)
+        k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+        return xs[k]
+
+    def as_dict(self):
+        return {"offered_req_per_s": self.offered_rate, "completed": self.completed,
+                "rejected": self.rejected, "numbers": self.numbers, "wall_s": round(self.wall_s, 4),
+                "numbers_per_s": self.numbers / self.wall_s if self.wall_s > 0 else math.nan,
+                "p50_ms": self.percentile(50) * 1e3, "p99_ms": self.percentile(99) * 1e3}
+
+
+class Server:
+    def __init__(self, executor: Executor, mem_budget_bytes: int = 8 << 30, chunk: int = 1 << 18,
+                 depth: int = 2, max_requests_per_tick: int = 1 << 16,
+                 clock: Callable[[], float] = time.perf_counter, keep_outputs: bool = True):
+        self.ex = executor
+        self.keep_outputs = keep_outputs
+        self.budget = mem_budget_bytes
+        self.chunk = chunk
+        self.depth = depth
+        self.max_per_tick = max_requests_per_tick
+        self.clock = clock
+        self.waiting: Deque[Request] = collections.deque()     # arrived, not admitted (FIFO)
+        self.active: Dict[int, Deque[Request]] = {}            # gen -> admitted, unfinished (FIFO)
+        self.inflight: Deque[Tuple[object, List[Tuple[Request, int]]]] = collections.deque()
+        self.in_use = 0
+        self.unscheduled = 0        # outputs admitted but not yet put in a tick
+        self.completed: List[Request] = []
+        self.rejected: List[Request] = []
+
+    # -- admission -----------------------------------------------------------
+    def submit(self, req: Request):
+        if req.nbytes > self.budget:
+            req.rejected = True
+            self.rejected.append(req)
+            return
+        self.waiting.append(req)
+
+    def _admit(self, now: float):
+        while self.waiting and self.in_use + self.waiting[0].nbytes <= self.budget:
+            r = self.waiting.popleft()
+            self.ex.alloc(r)
+            r.t_admit = now
+            self.in_use += r.nbytes
+            self.unscheduled += r.n
+            self.active.setdefault(r.gen, collections.deque()).append(r)
+
+    # -- ticks ---------------------------------------------------------------
+    def _build_tick(self) -> List[Tuple[Request, int]]:
+        picks = []
+        for gen, q in self.active.items():
+            # oldest request of this generator with work left to schedule
+            for r in q:
+                if r.done < r.n:
+                    k = min(self.chunk, r.n - r.done)
+                    picks.append((r, k))
+                    break
+            if len(picks) >= self.max_per_tick:
+                break
+        return picks
+
+    def _launch(self, picks):
+        chunks = [(r.gen, r.kind, k, r.out, r.done) for (r, k) in picks]
+        handle = self.ex.launch(chunks)       # nothing is committed if this raises
+        for r, k in picks:
+            r.done += k
+            self.unscheduled -= k
+        self.inflight.append((handle, picks))
+
+    def _retire(self, handle_picks, now: float):
+        _, picks = handle_picks
+        for r, k in picks:
+            r.finished += k
+            if r.finished == r.n:
+                r.t_done = now
+                self.in_use -= r.nbytes
+                q = self.active[r.gen]
+                q.remove(r)
+                if not q:
+                    del self.active[r.gen]
+                self.ex.free(r)
+                if not self.keep_outputs:
+                    r.out = None
+                self.completed.append(r)
+
+    def _pending_work(self) -> bool:
+        return self.unscheduled > 0
+
+    def step(self, now: float):
+        """Retire finished ticks, admit arrivals, and queue ticks up to `depth`."""
+        while self.inflight and self.ex.ready(self.inflight[0][0]):
+            self._retire(self.inflight.popleft(), now)
+        self._admit(now)
+        while len(self.inflight) < self.depth and self._pending_work():
+            self._launch(self._build_tick())
+
+    def drain(self):
+        while self.inflight:
+            h = self.inflight[0][0]
+            self.ex.wait(h)
+            self._retire(self.inflight.popleft(), self.clock())
+
+    # -- trace driver --------------------------------------------------------
+    def run(self, trace: Sequence[Tuple[float, int, int, int]], realtime: bool = True,
+            poll_s: float = 20e-6) -> ServeStats:
+        """trace: (arrival_s, gen, n, kind) sorted by arrival. With realtime,
+        requests are released when the wall clock reaches their arrival time;
+        otherwise all are available at once (saturation)."""
+        t0 = self.clock()
+        reqs = [Request(i, g, k, n, a if realtime else 0.0) for i, (a, g, n, k) in enumerate(trace)]
+        i = 0
+        while i < len(reqs) or self.waiting or self.active or self.inflight:
+            now = self.clock() - t0
+            while i < len(reqs) and reqs[i].arrival <= now:
+                self.submit(reqs[i])
+                i += 1
+            self.step(now)
+            if self.inflight and not self.ex.ready(self.inflight[0][0]):
+                # nothing to retire yet; wait for the next arrival or a short poll
+                nxt = reqs[i].arrival - now if i < len(reqs) else poll_s
+                if nxt > 0:
+                    time.sleep(min(poll_s, nxt))
+            elif not self.inflight and i < len(reqs) and not self.waiting:
+                dt = reqs[i].arrival - (self.clock() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            elif not self.inflight and not self.active and i >= len(reqs) and self.waiting:
+                # a request larger than the free budget with nothing in flight cannot happen
+                # (submit rejects requests above the whole budget); admit on the next step
+                pass
+        self.drain()
+        wall = self.clock() - t0
+        done = [r for r in reqs if not r.rejected and not math.isnan(r.t_done)]
+        lat = [r.t_done - r.arrival for r in done]
+        span = trace[-1][0] if (realtime and trace) else 0.0
+        rate = len(trace) / span if span > 0 else math.inf
+        return ServeStats(rate, len(done), len(self.rejected), sum(r.n for r in done), wall, lat)
