@@ -86,6 +86,28 @@ def cpu_baseline(params, n_per_gen, kinds, threads):
                       f"({total} numbers, {dt:.2f} s wall)"}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mtgp_kernel_headline_128x4M_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1005_4973_amd", "csrc", f) for f in ("mtgp_kernels.hip", "mtgp_internal.h")]
+
+
+def measured_traffic():
+    """HBM bytes per headline launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:")))
+    if fields.get("kernel_source_sha256_16", "").split()[0:1] != [h.hexdigest()[:16]]:
+        return None
+    return int(fields["traffic_bytes_per_launch"].strip())
+
+
 def timed_ms(torch, fn, reps=3):
     fn()
     torch.cuda.synchronize()
@@ -149,7 +171,7 @@ def headline(args, torch, I, mtgp):
         "value": round(numbers_per_step * args.steps / dt / 1e9, 3),
         "ms_per_step": round(dt / args.steps * 1e3, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "mtgp_kernel<false> (workgroup per generator)",
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                      "alg_bytes_per_launch": alg_bytes},
