@@ -162,6 +162,22 @@ void mtgp_batch_destroy(mtgp_batch_t *b);
  * error (see mtgp_last_error()).
  * ------------------------------------------------------------------------- */
 typedef struct mtgp_plan mtgp_plan_t;
+
+/*
+ * Jump-ahead for plans (the paper's section 7 discusses jumping ahead).
+ * With max_rounds > 0, mtgp_batch_plan_create splits every request whose
+ * generator would need more than max_rounds rounds into S segments of J
+ * outputs that run concurrently: segment k starts from the state F^{kJ} S,
+ * computed on the GPU at each launch as the XOR of the states S, F S, ...
+ * selected by h_k = x^{kJ} mod psi, where psi annihilates the generator's
+ * orbit (found once per generator on the host from the minimal polynomials of
+ * the bit planes of its raw words -- Berlekamp-Massey, section 5 -- and
+ * verified on every state word). Outputs are identical to the unsplit
+ * stream. A generator for which no annihilator is found is not split.
+ * mtgp_batch_set_state on a split generator makes existing plans stale
+ * (mtgp_plan_launch then returns MTGP_EINVAL). 0 (the default) disables it.
+ */
+int mtgp_batch_set_split(mtgp_batch_t *b, uint32_t max_rounds);
 mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq);
 int mtgp_plan_launch(mtgp_plan_t *p, void *stream);
 void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's last stream */

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libmtgp.so")
-SOURCES = [os.path.join(CSRC, "mtgp_kernels.hip"), os.path.join(CSRC, "mtgp_api.cpp")]
+SOURCES = [os.path.join(CSRC, "mtgp_kernels.hip"), os.path.join(CSRC, "mtgp_api.cpp"),
+           os.path.join(CSRC, "mtgp_f2.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -23,6 +24,7 @@ FLAGS = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
+    "-pthread",
 ]
 
 

@@ -3,13 +3,17 @@
 // the launch paths (single generator, persistent batch, one launch per
 // request, graph-captured plans).
 #include "../../include/mtgp.h"
+#include "mtgp_f2.h"
 #include "mtgp_internal.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <functional>
 #include <new>
+#include <thread>
 #include <vector>
 
 using namespace mtgp_impl;
@@ -211,6 +215,12 @@ struct mtgp_batch {
     size_t max_lds = 65536;
     bool have_override = false;
     LaunchShape override_shape;
+    // jump-ahead
+    std::vector<uint32_t> mexp;
+    uint32_t split_rounds = 0;                 // 0: never split a request
+    std::vector<uint64_t> epoch;               // bumped by set_state
+    std::vector<f2::Poly> psi;                 // annihilator of the generator's orbit (empty: none)
+    std::vector<uint64_t> psi_epoch;           // epoch + 1 when psi was computed, 0 if never
 };
 
 struct mtgp_plan {
@@ -222,17 +232,21 @@ struct mtgp_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     LaunchShape shape;
+    // jump-ahead segments
+    std::vector<uint32_t> split_gens;
+    std::vector<uint64_t> split_epochs;
+    void *d_jump_mem = nullptr;                // raw words, polynomials, segment states, prefix and jump items
 };
 
 namespace {
 
 // Default persistent launch shape for a batch (when no override is set):
-// - at most as many requests as CUs: one 256-lane workgroup per generator
-//   and one workgroup per CU (an exclusive LDS window), because each
-//   generator's rounds are latency-bound and two workgroups on one CU would
-//   share its issue slots;
-// - more requests: 256-lane workgroups with the smallest window that fits
-//   every request, so several generators share each CU.
+// 256-lane workgroups (one generator each, up to four steps per lane) and k
+// workgroups per CU, k = ceil(requests / CUs) capped by the resident-wave
+// limit. The LDS window is sized so that exactly k workgroups fit in a CU's
+// LDS and the grid is k * CUs: the hardware then has to place k workgroups on
+// every CU. (Left free, it packed several latency-bound generators onto one
+// CU while others idled.) k = 1 gives each generator a whole CU.
 LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem> &items)
 {
     LaunchShape s;
@@ -245,11 +259,15 @@ LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem>
         need = std::max(need, window_need(b->recs[it.gen], s));
     s.lds_words = 1;
     const uint32_t cap = max_window_words(s, b->max_lds);
-    if (items.size() <= (size_t)b->cu_count)
-        s.lds_words = (int)std::min(cap, std::max(need, kExclusiveWindow));
-    else
-        s.lds_words = (int)std::min(cap, std::max(need, 4096u));
-    s.grid = (int)std::min<uint64_t>(items.size(), resident_groups(s, b->cu_count));
+    const uint32_t by_waves = kWavesPerCu / (uint32_t)(s.threads / 64);
+    const uint64_t cus = (uint64_t)b->cu_count;
+    uint32_t k = (uint32_t)std::min<uint64_t>(by_waves, (items.size() + cus - 1) / cus);
+    k = std::max(k, 1u);
+    // bytes per workgroup, kept 1 KiB below an even share (allocation granularity)
+    const size_t share = (kLdsPerCu / k) / 1024u * 1024u - 1024u;
+    const uint32_t fit = (uint32_t)(share / 4u - kUnitLdsExtra);
+    s.lds_words = (int)std::min(cap, std::max(need, fit));
+    s.grid = (int)std::min<uint64_t>(items.size(), (uint64_t)k * cus);
     return s;
 }
 
@@ -361,7 +379,311 @@ void plan_free(mtgp_plan *p)
         hipStreamDestroy(p->capture);
     hipFree(p->d_items);
     hipFree(p->d_counters);
+    hipFree(p->d_jump_mem);
     delete p;
+}
+
+// ---------------------------------------------------------------------------
+// Jump-ahead (section 7): a request whose rounds exceed the batch's split
+// limit becomes S segments of J outputs; segment k starts from F^{kJ} S,
+// computed on the GPU as h_k(F) S with h_k = x^{kJ} mod psi, where psi
+// annihilates the generator's orbit.
+// ---------------------------------------------------------------------------
+
+void parallel_for(size_t n, const std::function<void(size_t)> &fn)
+{
+    size_t nt = std::max<size_t>(1u, std::min<size_t>(std::thread::hardware_concurrency(), 16u));
+    nt = std::min(nt, n);
+    std::atomic<size_t> next{0};
+    std::vector<std::thread> th;
+    for (size_t t = 0; t < nt; t++)
+        th.emplace_back([&] {
+            for (;;) {
+                const size_t i = next++;
+                if (i >= n)
+                    break;
+                fn(i);
+            }
+        });
+    for (auto &x : th)
+        x.join();
+}
+
+// True if sum_{i: phi_i = 1} X[i + w] = 0 for every w < N.
+bool annihilates(const f2::Poly &phi, const uint32_t *X, size_t len, uint32_t N)
+{
+    if (phi.deg < 0 || (size_t)phi.deg + N > len)
+        return false;
+    std::vector<uint32_t> acc(N, 0);
+    for (int64_t i = 0; i <= phi.deg; i++)
+        if (phi.bit(i))
+            for (uint32_t w = 0; w < N; w++)
+                acc[w] ^= X[i + w];
+    for (uint32_t w = 0; w < N; w++)
+        if (acc[w])
+            return false;
+    return true;
+}
+
+// Raw words needed to find an annihilator for exponent p: the N state words
+// and 2p + 65 new ones (Berlekamp-Massey needs twice the linear complexity,
+// which is at most p + 1 here).
+uint64_t raw_steps_for(uint32_t p) { return 2ull * p + 65; }
+
+// Annihilating polynomial of the orbit of the state X[0..N) (X continues with
+// the raw words that follow): the LCM of the minimal polynomials of the bit
+// planes of x_{c+1}, x_{c+2}, ... -- a polynomial annihilates the word
+// sequence exactly when it annihilates every bit plane -- taken until it
+// annihilates the state at c+1 (checked on all N words), then multiplied by x
+// so that it annihilates the state at c too (the transition may be singular).
+// Returns the zero polynomial if no annihilator is found.
+f2::Poly orbit_annihilator(const uint32_t *X, size_t len, uint32_t N, uint32_t p)
+{
+    const int64_t nbits = 2 * (int64_t)p + 64;
+    if ((size_t)nbits + 1 > len)
+        return f2::Poly();
+    static const int order[32] = {0, 16, 8, 24, 4, 12, 20, 28, 2, 6, 10, 14, 18, 22, 26, 30,
+                                  1, 3, 5, 7, 9, 11, 13, 15, 17, 19, 21, 23, 25, 27, 29, 31};
+    std::vector<uint64_t> packed((size_t)(nbits / 64 + 1));
+    f2::Poly phi = f2::Poly::one();
+    for (int bi = 0; bi < 32; bi++) {
+        const int b = order[bi];
+        std::fill(packed.begin(), packed.end(), 0);
+        for (int64_t j = 0; j < nbits; j++)
+            if ((X[1 + j] >> b) & 1u)
+                packed[(size_t)(j >> 6)] |= 1ull << (j & 63);
+        phi = f2::lcm(phi, f2::minpoly(packed.data(), nbits));
+        if (phi.deg > (int64_t)p + 1)
+            return f2::Poly();
+        if (annihilates(phi, X + 1, len - 1, N)) {
+            f2::Poly psi = f2::mul(phi, f2::Poly::from_words(std::vector<uint64_t>{2}.data(), 1));
+            return psi;
+        }
+    }
+    return f2::Poly();
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Shape of the prefix launch that writes raw words: 256 lanes per generator.
+LaunchShape raw_shape(const mtgp_batch *b, const std::vector<uint32_t> &gens)
+{
+    LaunchShape s;
+    s.mode = kModeGroup;
+    s.threads = 256;
+    s.spl = 4;
+    s.grid = (int)gens.size();
+    uint32_t need = 0;
+    for (uint32_t g : gens)
+        need = std::max(need, window_need(b->recs[g], s));
+    s.lds_words = (int)std::max(need, 4096u);
+    return s;
+}
+
+// Make sure every generator in `gens` has an annihilator for its current
+// orbit: raw words are generated on the GPU from the current states (the
+// states are not advanced) and reduced on the host.
+int ensure_annihilators(mtgp_batch *b, const std::vector<uint32_t> &gens)
+{
+    std::vector<uint32_t> todo;
+    for (uint32_t g : gens)
+        if (b->psi_epoch[g] != b->epoch[g] + 1)
+            todo.push_back(g);
+    if (todo.empty())
+        return MTGP_OK;
+    std::vector<WorkItem> items(todo.size());
+    std::vector<size_t> off(todo.size());
+    size_t total = 0;
+    for (size_t i = 0; i < todo.size(); i++) {
+        const GenRecord &r = b->recs[todo[i]];
+        off[i] = total;
+        total += r.N + raw_steps_for(b->mexp[todo[i]]);
+    }
+    const LaunchShape s = raw_shape(b, todo);
+    uint32_t *d_raw = nullptr;
+    WorkItem *d_items = nullptr;
+    hipStream_t st = nullptr;
+    int rc = MTGP_OK;
+    if (hipStreamSynchronize(b->last) != hipSuccess)
+        return MTGP_EDEVICE;
+    if (hipMalloc(&d_raw, total * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&d_items, items.size() * sizeof(WorkItem)) != hipSuccess) {
+        hipFree(d_raw);
+        return MTGP_ENOMEM;
+    }
+    for (size_t i = 0; i < todo.size(); i++) {
+        const GenRecord &r = b->recs[todo[i]];
+        std::memset(&items[i], 0, sizeof(WorkItem));
+        items[i].out = reinterpret_cast<uint64_t>(d_raw + off[i]);
+        items[i].n = raw_steps_for(b->mexp[todo[i]]);
+        items[i].gen = todo[i];
+        items[i].kind = kKindRaw | kKeepState;
+        items[i].spl = item_spl(r.N, r.M, s);
+    }
+    std::vector<uint32_t> raw(total);
+    WorkItem none;
+    std::memset(&none, 0, sizeof(none));
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        launch_generate(b->d_recs, b->d_states, d_items, (uint32_t)items.size(), nullptr, none, s, st) != hipSuccess ||
+        hipMemcpyAsync(raw.data(), d_raw, total * sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        rc = MTGP_EDEVICE;
+    if (st)
+        hipStreamDestroy(st);
+    hipFree(d_items);
+    hipFree(d_raw);
+    if (rc != MTGP_OK)
+        return rc;
+    parallel_for(todo.size(), [&](size_t i) {
+        const uint32_t g = todo[i];
+        const uint32_t N = b->recs[g].N;
+        b->psi[g] = orbit_annihilator(raw.data() + off[i], N + raw_steps_for(b->mexp[g]), N, b->mexp[g]);
+    });
+    for (uint32_t g : todo)
+        b->psi_epoch[g] = b->epoch[g] + 1;
+    return MTGP_OK;
+}
+
+struct SplitSpec {
+    size_t item;        // index in the request's item list
+    uint32_t gen;
+    uint32_t S;         // segments
+    uint64_t J;         // outputs per segment (the last one takes the rest)
+};
+
+// Split the plan's long requests into segments. Builds the prefix (raw words)
+// and jump work, lays out their device memory, and returns the new item list.
+int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem> &prefix,
+               std::vector<JumpItem> &jumps)
+{
+    mtgp_batch *b = p->b;
+    std::vector<SplitSpec> specs;
+    for (size_t i = 0; i < items.size(); i++) {
+        const GenRecord &r = b->recs[items[i].gen];
+        const uint64_t w = round_width(r.N, r.M, p->shape);
+        const uint64_t rounds = (items[i].n + w - 1) / w;
+        if (rounds <= b->split_rounds)
+            continue;
+        uint32_t S = (uint32_t)((rounds + b->split_rounds - 1) / b->split_rounds);
+        uint64_t J = (items[i].n + S - 1) / S;
+        while (S > 1 && (uint64_t)(S - 1) * J >= items[i].n) {
+            S--;
+            J = (items[i].n + S - 1) / S;
+        }
+        if (S > 1)
+            specs.push_back({i, items[i].gen, S, J});
+    }
+    if (specs.empty())
+        return MTGP_OK;
+    std::vector<uint32_t> gens;
+    for (const SplitSpec &sp : specs)
+        gens.push_back(sp.gen);
+    int rc = ensure_annihilators(b, gens);
+    if (rc != MTGP_OK)
+        return rc;
+    std::vector<SplitSpec> ok;
+    for (const SplitSpec &sp : specs)
+        if (b->psi[sp.gen].deg >= 1)
+            ok.push_back(sp);
+    if (ok.empty())
+        return MTGP_OK;
+    // jump polynomials h_k = x^{kJ} mod psi, k = 1 .. S-1
+    std::vector<std::vector<f2::Poly>> polys(ok.size());
+    parallel_for(ok.size(), [&](size_t i) {
+        const f2::Poly &psi = b->psi[ok[i].gen];
+        const f2::Poly g = f2::powmod_x(ok[i].J, psi);
+        polys[i].push_back(g);
+        for (uint32_t k = 2; k < ok[i].S; k++)
+            polys[i].push_back(f2::mulmod(polys[i].back(), g, psi));
+    });
+    // device layout: [raw words][polynomials][segment states]
+    std::vector<size_t> raw_off(ok.size()), poly_off(ok.size()), seg_off(ok.size());
+    size_t bytes = 0;
+    for (size_t i = 0; i < ok.size(); i++) {
+        const uint32_t N = b->recs[ok[i].gen].N;
+        const uint32_t D = (uint32_t)b->psi[ok[i].gen].deg;
+        raw_off[i] = bytes;
+        bytes = align256(bytes + (size_t)(N + D) * 4u);
+        poly_off[i] = bytes;
+        bytes = align256(bytes + (size_t)(ok[i].S - 1) * jump_poly_words(N, D) * 8u);
+        seg_off[i] = bytes;
+        bytes = align256(bytes + (size_t)(ok[i].S - 1) * N * 4u);
+    }
+    char *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess)
+        return MTGP_ENOMEM;
+    p->d_jump_mem = mem;
+    std::vector<uint64_t> hpoly(bytes / 8, 0);   // staging of the polynomial region (same offsets)
+    std::vector<WorkItem> out;
+    std::vector<bool> replaced(items.size(), false);
+    for (size_t i = 0; i < ok.size(); i++) {
+        const SplitSpec &sp = ok[i];
+        const WorkItem base = items[sp.item];
+        replaced[sp.item] = true;
+        const GenRecord &r = b->recs[sp.gen];
+        const uint32_t N = r.N;
+        const uint32_t D = (uint32_t)b->psi[sp.gen].deg;
+        const uint32_t pw = jump_poly_words(N, D);
+        const uint32_t R = jump_shape(N).R;
+        uint32_t *raw = reinterpret_cast<uint32_t *>(mem + raw_off[i]);
+        uint32_t *seg = reinterpret_cast<uint32_t *>(mem + seg_off[i]);
+        // prefix: the state and D - 1 new raw words (states stay put)
+        WorkItem pre;
+        std::memset(&pre, 0, sizeof(pre));
+        pre.out = reinterpret_cast<uint64_t>(raw);
+        pre.n = D - 1;
+        pre.gen = sp.gen;
+        pre.kind = kKindRaw | kKeepState;
+        prefix.push_back(pre);
+        for (uint32_t k = 1; k < sp.S; k++) {
+            const f2::Poly &h = polys[i][k - 1];
+            // bit e of h is bit e % R of block e / R (see JumpItem)
+            uint64_t *dst = hpoly.data() + (poly_off[i] / 8) + (size_t)(k - 1) * pw;
+            for (int64_t e = 0; e <= h.deg; e++)
+                if (h.bit(e)) {
+                    const uint64_t blk = (uint64_t)e / R;
+                    dst[blk / 4] |= 1ull << (16 * (blk % 4) + (uint64_t)e % R);
+                }
+            JumpItem j;
+            std::memset(&j, 0, sizeof(j));
+            j.raw = reinterpret_cast<uint64_t>(raw);
+            j.poly = reinterpret_cast<uint64_t>(mem + poly_off[i] + (size_t)(k - 1) * pw * 8u);
+            j.out = reinterpret_cast<uint64_t>(seg + (size_t)(k - 1) * N);
+            j.D = D;
+            j.N = N;
+            jumps.push_back(j);
+        }
+        for (uint32_t k = 0; k < sp.S; k++) {
+            WorkItem it = base;
+            const uint64_t start = (uint64_t)k * sp.J;
+            it.n = k + 1 < sp.S ? sp.J : base.n - start;
+            it.out = base.out + 4u * start;
+            it.src = k == 0 ? reinterpret_cast<uint64_t>(raw)
+                            : reinterpret_cast<uint64_t>(seg + (size_t)(k - 1) * N);
+            it.kind = (uint16_t)(base.kind | (k + 1 < sp.S ? kKeepState : 0));
+            out.push_back(it);
+        }
+        p->split_gens.push_back(sp.gen);
+        p->split_epochs.push_back(b->epoch[sp.gen]);
+    }
+    for (size_t i = 0; i < items.size(); i++)
+        if (!replaced[i])
+            out.push_back(items[i]);
+    items.swap(out);
+    // the jump kernel is launched once per lane width
+    std::stable_sort(jumps.begin(), jumps.end(), [](const JumpItem &x, const JumpItem &y) {
+        return jump_shape(x.N).R < jump_shape(y.N).R;
+    });
+    // upload the polynomials (only their regions are meaningful)
+    for (size_t i = 0; i < ok.size(); i++) {
+        const uint32_t D = (uint32_t)b->psi[ok[i].gen].deg;
+        const size_t len = (size_t)(ok[i].S - 1) * jump_poly_words(b->recs[ok[i].gen].N, D) * 8u;
+        if (hipMemcpy(mem + poly_off[i], hpoly.data() + poly_off[i] / 8, len, hipMemcpyHostToDevice) != hipSuccess)
+            return MTGP_EDEVICE;
+    }
+    return MTGP_OK;
 }
 
 }  // namespace
@@ -542,6 +864,12 @@ mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds,
     b->count = count;
     b->recs.resize(count);
     b->consumed.assign(count, 0);
+    b->mexp.resize(count);
+    for (uint32_t i = 0; i < count; i++)
+        b->mexp[i] = ps[i].mexp;
+    b->epoch.assign(count, 0);
+    b->psi.assign(count, f2::Poly());
+    b->psi_epoch.assign(count, 0);
     uint64_t off = 0;
     for (uint32_t i = 0; i < count; i++) {
         b->recs[i] = make_record(&ps[i], off);
@@ -683,6 +1011,14 @@ int mtgp_batch_set_launch(mtgp_batch_t *b, int mode, int threads, int spl, int l
     return MTGP_OK;
 }
 
+int mtgp_batch_set_split(mtgp_batch_t *b, uint32_t max_rounds)
+{
+    if (!b)
+        return fail(MTGP_EINVAL);
+    b->split_rounds = max_rounds;
+    return MTGP_OK;
+}
+
 int mtgp_batch_get_state(mtgp_batch_t *b, uint32_t gen, uint32_t *host_words, uint64_t *consumed)
 {
     if (!b || gen >= b->count || !host_words)
@@ -705,6 +1041,7 @@ int mtgp_batch_set_state(mtgp_batch_t *b, uint32_t gen, const uint32_t *host_wor
         hipMemcpy(b->d_states + r.state_off, host_words, r.N * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
         return fail(MTGP_EDEVICE);
     b->consumed[gen] = consumed;
+    b->epoch[gen]++;           // the orbit may have changed: annihilator and plans are stale
     return MTGP_OK;
 }
 
@@ -731,15 +1068,46 @@ mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, u
         fail(MTGP_EINVAL);
         return nullptr;
     }
+    std::vector<WorkItem> prefix;
+    std::vector<JumpItem> jumps;
+    if (b->split_rounds > 0) {
+        int rc = plan_split(p, p->items, prefix, jumps);
+        // the segments change the item count: size the launch for them
+        if (rc == MTGP_OK && !prefix.empty() && resolve_shape(b, p->items, p->shape) != MTGP_OK)
+            rc = MTGP_EINVAL;
+        if (rc != MTGP_OK) {
+            plan_free(p);
+            fail(rc);
+            return nullptr;
+        }
+    }
     finish_items(b, p->items, p->shape);
     const uint32_t nitems = (uint32_t)p->items.size();
-    if (hipMalloc(&p->d_items, nitems * sizeof(WorkItem)) != hipSuccess ||
+    const size_t extra = prefix.size() * sizeof(WorkItem) + jumps.size() * sizeof(JumpItem);
+    char *d_extra = nullptr;
+    if (hipMalloc(&p->d_items, nitems * sizeof(WorkItem) + extra) != hipSuccess ||
         hipMalloc(&p->d_counters, 2 * sizeof(uint32_t)) != hipSuccess) {
         plan_free(p);
         fail(MTGP_ENOMEM);
         return nullptr;
     }
+    d_extra = reinterpret_cast<char *>(p->d_items + nitems);
+    WorkItem *d_prefix = reinterpret_cast<WorkItem *>(d_extra);
+    JumpItem *d_jumps = reinterpret_cast<JumpItem *>(d_extra + prefix.size() * sizeof(WorkItem));
+    std::vector<uint32_t> pgens;
+    for (const WorkItem &it : prefix)
+        pgens.push_back(it.gen);
+    LaunchShape pshape;
+    if (!prefix.empty()) {
+        pshape = raw_shape(b, pgens);
+        for (WorkItem &it : prefix)
+            it.spl = item_spl(b->recs[it.gen].N, b->recs[it.gen].M, pshape);
+    }
     if (hipMemcpy(p->d_items, p->items.data(), nitems * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess ||
+        (!prefix.empty() &&
+         hipMemcpy(d_prefix, prefix.data(), prefix.size() * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!jumps.empty() &&
+         hipMemcpy(d_jumps, jumps.data(), jumps.size() * sizeof(JumpItem), hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemset(p->d_counters, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
         hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
         plan_free(p);
@@ -750,8 +1118,15 @@ mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, u
     std::memset(&none, 0, sizeof(none));
     bool ok = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-        const hipError_t le = launch_generate(b->d_recs, b->d_states, p->d_items, nitems, p->d_counters, none,
-                                              p->shape, p->capture);
+        hipError_t le = hipSuccess;
+        if (!prefix.empty())
+            le = launch_generate(b->d_recs, b->d_states, d_prefix, (uint32_t)prefix.size(), nullptr, none, pshape,
+                                 p->capture);
+        if (le == hipSuccess)
+            le = launch_jumps(d_jumps, jumps.data(), (uint32_t)jumps.size(), p->capture);
+        if (le == hipSuccess)
+            le = launch_generate(b->d_recs, b->d_states, p->d_items, nitems, p->d_counters, none, p->shape,
+                                 p->capture);
         const hipError_t ce = hipStreamEndCapture(p->capture, &p->graph);
         ok = le == hipSuccess && ce == hipSuccess && p->graph != nullptr;
     }
@@ -769,6 +1144,9 @@ int mtgp_plan_launch(mtgp_plan_t *p, void *stream)
 {
     if (!p)
         return fail(MTGP_EINVAL);
+    for (size_t i = 0; i < p->split_gens.size(); i++)
+        if (p->b->epoch[p->split_gens[i]] != p->split_epochs[i])
+            return fail(MTGP_EINVAL);   // a split generator's state was replaced: the plan is stale
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipGraphLaunch(p->exec, s) != hipSuccess)
         return fail(MTGP_EDEVICE);

@@ -1,0 +1,258 @@
+// Polynomial arithmetic over F2 for jump-ahead, on the host.
+//
+// A jump of J steps maps a state S to F^J S. If psi is a polynomial with
+// psi(F) S = 0, then F^J S = h(F) S for h = x^J mod psi, and h(F) S is the
+// sum of the states S, F S, F^2 S, ... selected by h's coefficients -- a
+// correlation of h with the stream of raw words (the paper's section 7 on
+// jumping ahead; the minimal polynomial of a bit sequence comes from the
+// Berlekamp-Massey algorithm, as in section 5).
+//
+// Polynomials are packed little-endian: bit k of word k/64 is the coefficient
+// of x^k.
+#include "mtgp_f2.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace mtgp_impl {
+namespace f2 {
+
+// ---------------------------------------------------------------------------
+// basics
+// ---------------------------------------------------------------------------
+
+void Poly::trim()
+{
+    int64_t d = (int64_t)w.size() * 64 - 1;
+    while (d >= 0 && !bit(d))
+        d--;
+    deg = d;
+    w.resize(d < 0 ? 0 : (size_t)(d / 64 + 1));
+}
+
+Poly Poly::one()
+{
+    Poly p;
+    p.w.assign(1, 1);
+    p.deg = 0;
+    return p;
+}
+
+Poly Poly::from_words(const uint64_t *src, int64_t deg)
+{
+    Poly p;
+    if (deg < 0)
+        return p;
+    p.w.assign(src, src + deg / 64 + 1);
+    p.trim();
+    return p;
+}
+
+// dst ^= src << shift (dst must be large enough)
+static void xor_shl(uint64_t *dst, const uint64_t *src, size_t nsrc, int64_t shift)
+{
+    const int64_t ws = shift >> 6;
+    const int bs = (int)(shift & 63);
+    if (bs == 0) {
+        for (size_t i = 0; i < nsrc; i++)
+            dst[ws + (int64_t)i] ^= src[i];
+        return;
+    }
+    uint64_t carry = 0;
+    for (size_t i = 0; i < nsrc; i++) {
+        dst[ws + (int64_t)i] ^= (src[i] << bs) | carry;
+        carry = src[i] >> (64 - bs);
+    }
+    if (carry)
+        dst[ws + (int64_t)nsrc] ^= carry;
+}
+
+// Carry-less product by shift-and-xor over the set bits of b (simple and
+// exact; used for all multiplications).
+static void clmul_words(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out)
+{
+    std::memset(out, 0, (na + nb + 1) * sizeof(uint64_t));
+    for (size_t j = 0; j < nb; j++) {
+        uint64_t bw = b[j];
+        while (bw) {
+            const int t = __builtin_ctzll(bw);
+            bw &= bw - 1;
+            xor_shl(out, a, na, (int64_t)(j * 64 + t));
+        }
+    }
+}
+
+Poly mul(const Poly &a, const Poly &b)
+{
+    Poly r;
+    if (a.deg < 0 || b.deg < 0)
+        return r;
+    r.w.resize(a.w.size() + b.w.size() + 1);
+    clmul_words(a.w.data(), a.w.size(), b.w.data(), b.w.size(), r.w.data());
+    r.trim();
+    return r;
+}
+
+Poly square(const Poly &a)
+{
+    Poly r;
+    if (a.deg < 0)
+        return r;
+    r.w.assign(2 * a.w.size(), 0);
+    for (size_t i = 0; i < a.w.size(); i++) {
+        uint64_t v = a.w[i];
+        uint64_t lo = 0, hi = 0;
+        for (int k = 0; k < 32; k++) {
+            lo |= ((v >> k) & 1ull) << (2 * k);
+            hi |= ((v >> (k + 32)) & 1ull) << (2 * k);
+        }
+        r.w[2 * i] = lo;
+        r.w[2 * i + 1] = hi;
+    }
+    r.trim();
+    return r;
+}
+
+// a mod m by shift-and-xor from the top down.
+Poly mod(const Poly &a, const Poly &m)
+{
+    Poly r = a;
+    if (m.deg < 0 || r.deg < m.deg)
+        return r;
+    for (int64_t d = r.deg; d >= m.deg; d--)
+        if (r.bit(d))
+            xor_shl(r.w.data(), m.w.data(), m.w.size(), d - m.deg);
+    r.trim();
+    return r;
+}
+
+Poly divide(const Poly &a, const Poly &m, Poly *rem)
+{
+    Poly q, r = a;
+    if (m.deg < 0)
+        return q;
+    if (r.deg >= m.deg) {
+        q.w.assign((size_t)((r.deg - m.deg) / 64 + 1), 0);
+        for (int64_t d = r.deg; d >= m.deg; d--)
+            if (r.bit(d)) {
+                xor_shl(r.w.data(), m.w.data(), m.w.size(), d - m.deg);
+                q.w[(size_t)((d - m.deg) >> 6)] |= 1ull << ((d - m.deg) & 63);
+            }
+    }
+    q.trim();
+    r.trim();
+    if (rem)
+        *rem = r;
+    return q;
+}
+
+Poly gcd(Poly a, Poly b)
+{
+    while (b.deg >= 0) {
+        Poly r = mod(a, b);
+        a = b;
+        b = r;
+    }
+    return a;
+}
+
+Poly lcm(const Poly &a, const Poly &b)
+{
+    if (a.deg < 0)
+        return b;
+    if (b.deg < 0)
+        return a;
+    const Poly g = gcd(a, b);
+    return mul(a, divide(b, g, nullptr));
+}
+
+Poly mulmod(const Poly &a, const Poly &b, const Poly &m) { return mod(mul(a, b), m); }
+
+Poly powmod_x(uint64_t e, const Poly &m)
+{
+    Poly r = Poly::one();
+    if (m.deg <= 0)
+        return Poly();
+    r = mod(r, m);
+    int top = 63;
+    while (top >= 0 && !((e >> top) & 1))
+        top--;
+    for (int k = top; k >= 0; k--) {
+        r = mod(square(r), m);
+        if ((e >> k) & 1) {
+            // r *= x
+            Poly s;
+            s.w.assign(r.w.size() + 1, 0);
+            xor_shl(s.w.data(), r.w.data(), r.w.size(), 1);
+            s.trim();
+            r = mod(s, m);
+        }
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Berlekamp-Massey (J. L. Massey, 1969) on a packed bit sequence.
+// ---------------------------------------------------------------------------
+
+Poly minpoly(const uint64_t *bits, int64_t n)
+{
+    // Work on the reversed sequence, so that s_j, s_{j-1}, ..., s_{j-L} is a
+    // forward run of bits starting at reversed position n-1-j.
+    const size_t nw = (size_t)(n / 64 + 4);
+    std::vector<uint64_t> rs(nw, 0);
+    for (int64_t j = 0; j < n; j++)
+        if ((bits[j >> 6] >> (j & 63)) & 1)
+            rs[(size_t)((n - 1 - j) >> 6)] |= 1ull << ((n - 1 - j) & 63);
+    auto window = [&](int64_t pos) -> uint64_t {
+        const size_t wi = (size_t)(pos >> 6);
+        const int b = (int)(pos & 63);
+        const uint64_t lo = wi < nw ? rs[wi] : 0;
+        const uint64_t hi = wi + 1 < nw ? rs[wi + 1] : 0;
+        return b ? (lo >> b) | (hi << (64 - b)) : lo;
+    };
+    // C: connection polynomial (c_0 = 1), B: the one before the last length
+    // change; deg(x^m B) <= n always, so only B's low (n - m)/64 + 2 words can
+    // be non-zero, and C needs n/64 + 4 words.
+    std::vector<uint64_t> C(nw, 0), B(nw, 0), T;
+    C[0] = 1;
+    B[0] = 1;
+    int64_t L = 0, m = 1;
+    auto add_shifted_B = [&]() {
+        const size_t nb = std::min(nw - (size_t)(m >> 6) - 1, (size_t)((n - m) / 64 + 2));
+        xor_shl(C.data(), B.data(), nb, m);
+    };
+    for (int64_t j = 0; j < n; j++) {
+        uint64_t acc = 0;
+        const int64_t base = n - 1 - j;
+        for (int64_t i = 0; i <= L; i += 64) {
+            uint64_t cw = C[(size_t)(i >> 6)];
+            if (L - i < 63)
+                cw &= ((1ull << (L - i + 1)) - 1);
+            acc ^= cw & window(base + i);
+        }
+        if (!__builtin_parityll(acc)) {
+            m++;
+        } else if (2 * L <= j) {
+            T = C;
+            add_shifted_B();
+            L = j + 1 - L;
+            B = T;
+            m = 1;
+        } else {
+            add_shifted_B();
+            m++;
+        }
+    }
+    // characteristic form: phi(x) = x^L C(1/x), phi_i = c_{L-i}
+    Poly phi;
+    phi.w.assign((size_t)(L / 64 + 1), 0);
+    for (int64_t i = 0; i <= L; i++)
+        if ((C[(size_t)((L - i) >> 6)] >> ((L - i) & 63)) & 1)
+            phi.w[(size_t)(i >> 6)] |= 1ull << (i & 63);
+    phi.trim();
+    return phi;
+}
+
+}  // namespace f2
+}  // namespace mtgp_impl

@@ -22,15 +22,88 @@ struct alignas(256) GenRecord {
 };
 static_assert(sizeof(GenRecord) == 256, "GenRecord layout");
 
-// One unit of work: n outputs of `kind` from generator `gen` into `out`.
+// Output kinds of a work item (low byte of WorkItem::kind).
+constexpr uint16_t kKindU32 = 0;     // tempered uint32
+constexpr uint16_t kKindF12 = 1;     // float [1,2)
+constexpr uint16_t kKindF01 = 2;     // float [0,1)
+constexpr uint16_t kKindRaw = 3;     // untempered words: the N start words, then x_{c+N}, x_{c+N+1}, ...
+constexpr uint16_t kKeepState = 0x100;   // flag: do not write the end state back to the generator
+
+// One unit of work: n outputs of `kind` from generator `gen` into `out`,
+// starting from the generator's resident state, or from `src` if non-zero.
 struct alignas(32) WorkItem {
     uint64_t out;        // device address of the first output word
     uint64_t n;          // outputs to produce
     uint32_t gen;        // index into the GenRecord array
-    uint16_t kind;       // 0 uint32, 1 float [1,2), 2 float [0,1)
+    uint16_t kind;       // kind in the low byte, kKeepState flag
     uint16_t spl;        // steps per lane per round for this item
-    uint64_t reserved;   // 0
+    uint64_t src;        // device address of N start words, or 0 for the generator's state
 };
+
+// One jump: out[w] = XOR over the set bits i of h (D bits) of raw[i + w], for
+// w < N. raw holds D + N - 1 consecutive words of a stream starting at the
+// state to jump from. h is laid out for the kernel's geometry (JumpShape): in
+// blocks of R bits, block k = bits [kR, kR + R) of h in the low bits of a
+// 16-bit field, four blocks per 64-bit word (block k in bits 16 (k % 4) of
+// word k / 4), ceil(D / 4R) words.
+struct alignas(32) JumpItem {
+    uint64_t raw;
+    uint64_t poly;
+    uint64_t out;
+    uint32_t D;
+    uint32_t N;
+};
+static_assert(sizeof(JumpItem) == 32, "JumpItem layout");
+
+// Geometry of the jump kernel for a state of N words: a lane owns R
+// consecutive words (6 <= R <= 16), a wavefront covers 64 R words, G
+// wavefronts cover the N words and the P = 4 / G wavefronts of each word group
+// split the bits of h. raw is staged through LDS CI iterations of 4R bits at a
+// time. Per bit of h a wavefront does about R / 2 XORs and one cross-lane move
+// per lane, so R is chosen for the least G (R + 2), then for all four
+// wavefronts busy, then the smaller R.
+struct JumpShape {
+    uint32_t R, G, P, CI;
+};
+constexpr uint32_t kJumpStageBits = 8192;   // raw words per LDS stage, at most
+constexpr uint32_t kJumpMinR = 6, kJumpMaxR = 16;
+
+__host__ __device__ inline JumpShape jump_shape(uint32_t N)
+{
+    JumpShape best = {0, 0, 0, 0};
+    uint32_t best_cost = 0;
+    for (uint32_t R = kJumpMinR; R <= kJumpMaxR; R++) {
+        const uint32_t G = (N + 64 * R - 1) / (64 * R);
+        if (G > 4)
+            continue;
+        const uint32_t cost = G * (R + 2);
+        const bool better = best.R == 0 || cost < best_cost ||
+                            (cost == best_cost && (4 / G) * G > best.P * best.G);
+        if (better) {
+            best = {R, G, 4 / G, kJumpStageBits / (4 * R)};
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+// 64-bit words of h in the jump kernel's layout for a D-bit h.
+__host__ __device__ inline uint32_t jump_poly_words(uint32_t N, uint32_t D)
+{
+    const uint32_t step = 4 * jump_shape(N).R;
+    return (D + step - 1) / step;
+}
+
+// LDS words the jump kernel uses for a state of N words: a stage of raw words,
+// the N - 1 words past it rounded up to the word groups plus the window
+// read-ahead, then CI 64-bit words of h.
+__host__ __device__ inline uint32_t jump_lds_words(uint32_t N)
+{
+    const JumpShape s = jump_shape(N);
+    const uint32_t raw = 4 * s.R * s.CI + s.G * 64 * s.R + 6 * s.R;
+    return (raw + 1) / 2 * 2 + 2 * s.CI;
+}
+
 static_assert(sizeof(WorkItem) == 32, "WorkItem layout");
 
 // Launch shape of the generation kernels.
@@ -85,6 +158,11 @@ inline uint32_t round_span(uint32_t N, uint32_t M, const LaunchShape &s)
 hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkItem *items,
                            uint32_t nitems, uint32_t *counters, const WorkItem &single,
                            const LaunchShape &shape, hipStream_t stream);
+
+// One workgroup of 256 lanes per jump item (geometry jump_shape(N)); d_items
+// on the device, h_items the same items on the host, grouped by lane width
+// (one launch per run of equal widths).
+hipError_t launch_jumps(const JumpItem *d_items, const JumpItem *h_items, uint32_t nitems, hipStream_t stream);
 
 // Allow every generation kernel to use up to `bytes` of dynamic LDS.
 hipError_t opt_in_lds(size_t bytes);

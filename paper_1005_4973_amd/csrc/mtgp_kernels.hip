@@ -49,6 +49,8 @@ __device__ __forceinline__ uint32_t output_word(uint32_t x, uint32_t tv)
 {
     if constexpr (KIND == 0) {
         return x ^ tv;
+    } else if constexpr (KIND == 3) {
+        return x;   // untempered word (input of the jump correlation)
     } else {
         const uint32_t b = (x >> 9) ^ tv;
         if constexpr (KIND == 1) {
@@ -164,8 +166,9 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const uint3
         base += rem;
     }
     // x_n .. x_{n+N-1} back to HBM (section 8: the next call continues)
-    for (uint32_t k = lane; k < N; k += T)
-        state[k] = X[base + k];
+    if (state != nullptr)
+        for (uint32_t k = lane; k < N; k += T)
+            state[k] = X[base + k];
 }
 
 // ---------------------------------------------------------------------------
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
     const uint32_t units = WAVE ? (blockDim.x >> 6) : 1u;
     uint32_t *rec = smem + unit * (kTableWords + L);
     uint32_t *otb = rec + 16;
-    uint32_t *slot = rec + 32;
+    uint32_t *qslot = rec + 32;
     uint32_t *X = rec + kTableWords;
 
     for (uint32_t iter = 0;; ++iter) {
@@ -247,9 +250,9 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
                 q = __builtin_amdgcn_readfirstlane(q);
             } else {
                 if (lane == 0)
-                    slot[0] = atomicAdd(&counters[0], 1u);
+                    qslot[0] = atomicAdd(&counters[0], 1u);
                 __syncthreads();
-                q = __builtin_amdgcn_readfirstlane(slot[0]);
+                q = __builtin_amdgcn_readfirstlane(qslot[0]);
                 __syncthreads();
             }
             if (q >= nitems)
@@ -257,15 +260,18 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             it = items[q];
         }
         const uint32_t gen = __builtin_amdgcn_readfirstlane(it.gen);
-        const uint32_t kind = __builtin_amdgcn_readfirstlane((uint32_t)it.kind);
+        const uint32_t flags = __builtin_amdgcn_readfirstlane((uint32_t)it.kind);
+        const uint32_t kind = flags & 0xffu;
         const uint32_t spl = __builtin_amdgcn_readfirstlane((uint32_t)it.spl);
         const GenRecord &g = recs[gen];
         const uint32_t N = g.N, M = g.M;
-        uint32_t *state = states + g.state_off;
+        uint32_t *slot = states + g.state_off;
+        const uint32_t *from = it.src ? reinterpret_cast<const uint32_t *>(it.src) : slot;
+        uint32_t *state = (flags & kKeepState) ? nullptr : slot;
         const uint32_t W = (N - M) < T * spl ? (N - M) : T * spl;
 
         for (uint32_t k = lane; k < N; k += T)
-            X[k] = state[k];
+            X[k] = from[k];
         if (lane < 16) {
             rec[lane] = g.rec[lane];
             otb[lane] = kind == 0 ? g.tmp[lane] : g.flt[lane];
@@ -274,12 +280,20 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             __syncthreads();
 
         gu32 *out = reinterpret_cast<gu32 *>(it.out);
-        if (kind == 0)
+        if (kind == kKindRaw) {
+            // the start words first, then the new words
+            for (uint32_t k = lane; k < N; k += T)
+                out[k] = X[k];
+            out += N;
+        }
+        if (kind == kKindU32)
             run_item<0, WAVE>(spl, X, rec, otb, g, W, L, it.n, out, state, lane, T);
-        else if (kind == 1)
+        else if (kind == kKindF12)
             run_item<1, WAVE>(spl, X, rec, otb, g, W, L, it.n, out, state, lane, T);
-        else
+        else if (kind == kKindF01)
             run_item<2, WAVE>(spl, X, rec, otb, g, W, L, it.n, out, state, lane, T);
+        else
+            run_item<3, WAVE>(spl, X, rec, otb, g, W, L, it.n, out, state, lane, T);
         if (!WAVE)
             __syncthreads();   // the next item overwrites the window and tables
     }
@@ -309,6 +323,188 @@ hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkIt
         hipLaunchKernelGGL(mtgp_kernel<true>, grid, block, lds, stream, recs, states, items, nitems, counters,
                            single, L);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Jump correlation: a start state F^J S = h(F) S as the XOR of the states
+// S, F S, F^2 S, ... selected by the coefficients of h = x^J mod psi (psi an
+// annihilating polynomial of S), i.e. out[w] = XOR_{i: h_i = 1} raw[i + w].
+//
+// One workgroup of 4 wavefronts per jump. Lane l of wavefront g owns the R
+// consecutive words w0 .. w0+R-1 (w0 = 64 R g + R l) and slides a 2R-word
+// window (lo, hi) = raw[i + w0 .. i + w0 + 2R) over the bits of h: per block
+// of R bits it XORs, for each set bit t (a uniform scalar test), the window
+// words t .. t+R-1 into its sums, so a clear bit costs no vector work. The
+// window then moves on by R words: the new lo is the old hi, and the new hi is
+// the next lane's new lo, taken across lanes with a wave-wide DPP shift; only
+// the top lane's R words come from LDS, as a broadcast read. The P wavefronts
+// of a word group split the bits of h and add their partial sums through LDS
+// at the end. The block bits come from h's 64-bit words, staged in LDS beside
+// raw and read one iteration ahead.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kJumpLanes = 256;
+constexpr int kDppWaveShl1 = 0x130;   // DPP control: lane k reads lane k + 1; lane 63 keeps `old`
+
+// One block: R bits hb of h over the window (lo, hi); then nx = the next hi,
+// shifted in from lane + 1, with the top lane's words read from top[].
+template <uint32_t R>
+__device__ __forceinline__ void jump_block(uint32_t (&acc)[R], const uint32_t (&lo)[R], const uint32_t (&hi)[R],
+                                           uint32_t (&nx)[R], const uint32_t *top, uint32_t hb)
+{
+    uint32_t ext[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++)
+        ext[r] = top[r];   // same address in every lane: an LDS broadcast
+#pragma unroll
+    for (uint32_t t = 0; t < R; t++) {
+        if ((hb >> t) & 1u) {   // uniform: a clear bit costs no vector work
+            // an empty volatile asm keeps the compiler from turning the
+            // branch into XORs and selects for every bit
+            asm volatile("");
+#pragma unroll
+            for (uint32_t r = 0; r < R; r++)
+                acc[r] ^= (t + r < R) ? lo[t + r] : hi[t + r - R];
+        }
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++)
+        nx[r] = (uint32_t)__builtin_amdgcn_update_dpp((int)ext[r], (int)hi[r], kDppWaveShl1, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <uint32_t R>
+__global__ __launch_bounds__(256) void mtgp_jump_kernel(const JumpItem *__restrict__ items)
+{
+    extern __shared__ uint32_t Xs[];
+    const JumpItem it = items[blockIdx.x];
+    constexpr uint32_t W = 64 * R;          // words per wavefront
+    constexpr uint32_t STEP = 4 * R;        // bits (and raw words) per iteration
+    const JumpShape sh = jump_shape(it.N);  // sh.R == R
+    const uint32_t N = it.N, D = it.D;
+    const uint32_t G = sh.G, P = sh.P, CI = sh.CI;
+    const uint32_t raw_words = 4 * R * CI + G * W + 6 * R;
+    uint64_t *Ps = reinterpret_cast<uint64_t *>(Xs + (raw_words + 1) / 2 * 2);
+    const uint32_t *raw = reinterpret_cast<const uint32_t *>(it.raw);
+    const uint64_t *poly = reinterpret_cast<const uint64_t *>(it.poly);
+    uint32_t *out = reinterpret_cast<uint32_t *>(it.out);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    const bool active = wave < G * P;
+    const uint32_t grp = wave % G;
+    const uint32_t part = wave / G;
+    const uint32_t w0 = grp * W + lane * R;
+    const uint32_t wtop = (grp + 1) * W;            // first word past this wavefront's words
+    const uint32_t iters = (D + STEP - 1) / STEP;   // 64-bit words of h
+
+    uint32_t acc[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; r++)
+        acc[r] = 0;
+
+    for (uint32_t s0 = 0; s0 < iters; s0 += CI) {
+        const uint32_t ci = iters - s0 < CI ? iters - s0 : CI;
+        const uint32_t i0 = s0 * STEP;
+        const uint32_t cnt = D - i0 < ci * STEP ? D - i0 : ci * STEP;
+        for (uint32_t k = threadIdx.x; k < cnt + N - 1; k += kJumpLanes)
+            Xs[k] = raw[i0 + k];
+        for (uint32_t k = threadIdx.x; k < ci; k += kJumpLanes)
+            Ps[k] = poly[s0 + k];
+        __syncthreads();
+        if (active) {
+            // this wavefront's iterations of the stage: [q0, q1)
+            const uint32_t per = (ci + P - 1) / P;
+            const uint32_t q0 = part * per;
+            const uint32_t q1 = q0 + per < ci ? q0 + per : ci;
+            uint32_t A[R], B[R];
+            if (q0 < q1) {
+                uint32_t ext[R];
+#pragma unroll
+                for (uint32_t r = 0; r < R; r++) {
+                    A[r] = Xs[q0 * STEP + w0 + r];
+                    ext[r] = Xs[q0 * STEP + wtop + r];
+                }
+#pragma unroll
+                for (uint32_t r = 0; r < R; r++)
+                    B[r] = (uint32_t)__builtin_amdgcn_update_dpp((int)ext[r], (int)A[r], kDppWaveShl1, 0xf, 0xf,
+                                                                 false);
+            }
+            uint64_t hw = q0 < q1 ? uniform64(Ps[q0]) : 0;
+            for (uint32_t q = q0; q < q1; q++) {
+                const uint64_t hn = q + 1 < q1 ? uniform64(Ps[q + 1]) : 0;
+                // the top lane's next hi for block b is raw[i + (b + 2) R + wtop ..]
+                const uint32_t *top = Xs + q * STEP + wtop;
+                jump_block<R>(acc, A, B, A, top + 1 * R, (uint32_t)hw & 0xffffu);
+                jump_block<R>(acc, B, A, B, top + 2 * R, (uint32_t)(hw >> 16) & 0xffffu);
+                jump_block<R>(acc, A, B, A, top + 3 * R, (uint32_t)(hw >> 32) & 0xffffu);
+                jump_block<R>(acc, B, A, B, top + 4 * R, (uint32_t)(hw >> 48));
+                hw = hn;
+            }
+        }
+        __syncthreads();
+    }
+    // partial sums of the P wavefronts of each word group, through LDS
+    if (P > 1) {
+        if (active && part > 0)
+#pragma unroll
+            for (uint32_t r = 0; r < R; r++)
+                Xs[(part - 1) * (G * W) + w0 + r] = acc[r];
+        __syncthreads();
+        if (active && part == 0)
+            for (uint32_t q = 1; q < P; q++)
+#pragma unroll
+                for (uint32_t r = 0; r < R; r++)
+                    acc[r] ^= Xs[(q - 1) * (G * W) + w0 + r];
+    }
+    if (active && part == 0)
+#pragma unroll
+        for (uint32_t r = 0; r < R; r++)
+            if (w0 + r < N)
+                out[w0 + r] = acc[r];
+}
+
+template <uint32_t R>
+hipError_t launch_jump_run(const JumpItem *items, uint32_t n, size_t lds, hipStream_t stream)
+{
+    hipLaunchKernelGGL(mtgp_jump_kernel<R>, dim3(n), dim3(kJumpLanes), lds, stream, items);
+    return hipGetLastError();
+}
+
+template <uint32_t R>
+hipError_t launch_jump_width(uint32_t width, const JumpItem *items, uint32_t n, size_t lds, hipStream_t stream)
+{
+    if constexpr (R > kJumpMaxR) {
+        return hipErrorInvalidValue;
+    } else {
+        return width == R ? launch_jump_run<R>(items, n, lds, stream)
+                          : launch_jump_width<R + 1>(width, items, n, lds, stream);
+    }
+}
+
+hipError_t launch_jumps(const JumpItem *d_items, const JumpItem *h_items, uint32_t nitems, hipStream_t stream)
+{
+    // one launch per run of items with the same lane width
+    uint32_t k = 0;
+    while (k < nitems) {
+        const uint32_t R = jump_shape(h_items[k].N).R;
+        uint32_t e = k;
+        uint32_t words = 0;
+        while (e < nitems && jump_shape(h_items[e].N).R == R) {
+            words = jump_lds_words(h_items[e].N) > words ? jump_lds_words(h_items[e].N) : words;
+            e++;
+        }
+        const hipError_t err = launch_jump_width<kJumpMinR>(R, d_items + k, e - k, (size_t)words * 4u, stream);
+        if (err != hipSuccess)
+            return err;
+        k = e;
+    }
+    return hipSuccess;
 }
 
 hipError_t opt_in_lds(size_t bytes)

@@ -71,6 +71,7 @@ _SIGNATURES = {
     "mtgp_batch_destroy": (None, [ctypes.c_void_p]),
     "mtgp_batch_plan_create": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32]),
     "mtgp_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_batch_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_plan_destroy": (None, [ctypes.c_void_p]),
     "mtgp_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 5),
     "mtgp_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 4),
@@ -241,6 +242,10 @@ class Batch:
     def generate_plain(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
         arr, k = self._reqs(requests)
         _check(lib().mtgp_batch_generate_plain(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate_plain")
+
+    def set_split(self, max_rounds: int):
+        """Split plan requests longer than max_rounds rounds into jump-ahead segments (0: off)."""
+        _check(lib().mtgp_batch_set_split(self._h, max_rounds), "mtgp_batch_set_split")
 
     def plan(self, requests: Iterable) -> "Plan":
         """Capture the persistent launch for a fixed request list (see Plan)."""

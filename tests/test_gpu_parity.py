@@ -288,3 +288,51 @@ def test_plan_graph_replays(M):
         np.testing.assert_array_equal(w, states[g])
     plan.close()
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# Jump-ahead: split plans give the unsplit stream's bits
+# ---------------------------------------------------------------------------
+
+def test_plan_split_jump_ahead(M):
+    import json
+    import torch
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fullperiod_sets.json")))
+    full = [I.ParamSet(e["mexp"], e["pos"], e["sh1"], e["sh2"], tuple(e["param_tbl"]), tuple(e["temper_tbl"]))
+            for e in d["sets"] if e["mexp"] >= 521]
+    params = (I.draw_param_sets([11213] * 3, 71) + I.draw_param_sets([11213], 72, I.M_POLICY_WIDE)
+              + I.draw_param_sets([23209], 73) + I.draw_param_sets([44497], 74)
+              # state sizes for every lane width of the jump kernel (6 .. 16 words a lane)
+              + I.draw_param_sets([15000, 65536, 12315, 16411, 18459, 24603, 26651, 28699], 76) + full)
+    seeds = I.state_seeds(len(params))
+    b = M.Batch(params, seeds)
+    b.set_split(6)
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    rng = I.SplitMix64(75)
+    reqs = [(g, g % 3, rng.uniform_int(30000, 90000)) for g in range(len(params))]
+    bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+    # an eager call first, so the plan starts mid-stream
+    eb = [torch.empty(777, dtype=torch.int32, device="cuda") for _ in params]
+    b.generate([(g, 0, 777, eb[g]) for g in range(len(params))])
+    for g in range(len(params)):
+        np.testing.assert_array_equal(host_bits(eb[g]), O.generate(params[g], states[g], 777, 0))
+    plan = b.plan([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+    for rep in range(3):
+        say(f"split plan replay {rep}")
+        plan.launch()
+        torch.cuda.synchronize()
+        for (g, k, n), buf in zip(reqs, bufs):
+            ref = O.generate(params[g], states[g], n, k)
+            np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"replay={rep} gen={g} mexp={params[g].mexp}")
+        b.generate([(g, 1, 333, eb[g]) for g in range(len(params))])
+        torch.cuda.synchronize()
+        for g in range(len(params)):
+            np.testing.assert_array_equal(host_bits(eb[g])[:333], O.generate(params[g], states[g], 333, 1))
+    for g in range(len(params)):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g])
+    # replacing a split generator's state makes the plan stale
+    b.set_state(0, states[0], 0)
+    with pytest.raises(M.MTGPError):
+        plan.launch()
+    plan.close()
+    b.close()
