@@ -3,17 +3,21 @@
 Headline step (`value`): the 128-generator workload -- 128 distinct
 MTGP-11213 generators (M drawn by the paper's thread-count rule), 2^22
 outputs each, generated as uint32, then float32 in [1,2), then float32 in
-[0,1): three persistent batched launches (one per output kind), each a
-replay of a HIP-graph-captured plan writing 2 GiB. Every launch loads each
-state into LDS, runs the recursion rounds with tempering and conversion,
-stores outputs with nontemporal writes, and stores the states back.
+[0,1): three replays of HIP-graph-captured plans (one per output kind),
+each writing 2 GiB. The batch's launch shape and jump-ahead split limit are
+autotuned once, before the timed region. A replay first computes the start
+states of each stream's segments (a raw-word prefix and the jump
+correlations), then runs the persistent generation kernel: every segment's
+state is loaded into LDS, the recursion rounds run with tempering and
+conversion, outputs leave with nontemporal stores, and each generator's end
+state is stored back.
 
 The same JSON line also reports:
   batched_uneven  4096 generators (2:1:1 over p = 11213, 23209, 44497),
                   lengths log-uniform in [2^10, 2^24], mixed kinds: one
                   graph-captured persistent launch vs one launch per request
   large_states    256 generators at p = 23209 and at p = 44497, 2^24 uint32 each
-  single_stream   one MTGP-11213 generator, 2^20 uint32
+  single_stream   one MTGP-11213 generator, 2^20 uint32 (one eager call)
   serving         65536 resident MTGP-11213 states, Poisson arrivals at a swept
                   fraction of the measured saturation rate, log-normal sizes
                   (median 2^16, sigma 1.5, clipped to [2^10, 2^26]):
@@ -90,9 +94,10 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mtgp_kernel_headline_128x4M_tr
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1005_4973_amd", "csrc", f) for f in ("mtgp_kernels.hip", "mtgp_internal.h")]
 
 
-def measured_traffic():
-    """HBM bytes per headline launch from the committed counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+def measured_traffic(tuning):
+    """HBM bytes per launch of the headline generation kernel from the committed
+    counter summary, or None when the kernel sources or the tuned configuration
+    differ from those the counters were taken with."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -102,8 +107,10 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
     fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:")))
+                  if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:", "split_rounds:")))
     if fields.get("kernel_source_sha256_16", "").split()[0:1] != [h.hexdigest()[:16]]:
+        return None
+    if fields.get("split_rounds", "").strip() != str(tuning["split_rounds"]):
         return None
     return int(fields["traffic_bytes_per_launch"].strip())
 
@@ -133,47 +140,58 @@ def headline(args, torch, I, mtgp):
     kinds = (I.KIND_U32, I.KIND_F12, I.KIND_F01)
     batch = mtgp.Batch(params, I.state_seeds(G))
     out = torch.empty(G * n, dtype=torch.int32, device="cuda")
-    plans = [batch.plan([(g, k, n, out.data_ptr() + 4 * g * n) for g in range(G)]) for k in kinds]
     stream = torch.cuda.current_stream()
+    reqs = {k: [(g, k, n, out.data_ptr() + 4 * g * n) for g in range(G)] for k in kinds}
+    # launch shape and jump-ahead split limit, tuned on the uint32 requests
+    # (outputs are identical under every choice; states are left untouched)
+    tuning = batch.autotune(reqs[I.KIND_U32], reps=3, stream=stream)
+    log(f"autotune: {tuning}")
+    plans = [batch.plan(reqs[k]) for k in kinds]
 
     for _ in range(args.warmup):
         for p in plans:
             p.launch(stream)
     torch.cuda.synchronize()
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps * len(kinds))]
+    # each launch as its two phases, with events around the generation phase:
+    # segment start states (raw prefix + jump kernels), then the persistent
+    # generation kernel, the dominant one
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps * len(kinds))]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = 0
     for _ in range(args.steps):
         for p in plans:
             ev[i][0].record(stream)
-            p.launch(stream)
+            p.launch_phase(mtgp.PHASE_PREPARE, stream)
             ev[i][1].record(stream)
+            p.launch_phase(mtgp.PHASE_GENERATE, stream)
+            ev[i][2].record(stream)
             i += 1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
     numbers_per_step = G * n * len(kinds)
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
-    avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+    gen_ms = [b.elapsed_time(c) for a, b, c in ev]
+    prep_ms = [a.elapsed_time(b) for a, b, c in ev]
+    avg_gen_s = sum(gen_ms) / len(gen_ms) / 1e3
     N = 351
     # algorithmic bytes of one launch: outputs + state in and out + parameter record
     alg_bytes = G * (4 * n + 8 * N + 256)
-    achieved = alg_bytes / avg_launch_s / 1e9
+    achieved = alg_bytes / avg_gen_s / 1e9
     for p in plans:
         p.close()
     batch.close()
     del out
     torch.cuda.empty_cache()
-    return params, n, kinds, {
+    return params, n, kinds, tuning, {
         "value": round(numbers_per_step * args.steps / dt / 1e9, 3),
         "ms_per_step": round(dt / args.steps * 1e3, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "mtgp_kernel<false> (workgroup per generator)",
-                     "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(tuning),
+                     "kernel": "mtgp_kernel<false> (persistent generation over jump-ahead segments)",
+                     "avg_launch_ms": round(avg_gen_s * 1e3, 4),
+                     "avg_prepare_ms": round(sum(prep_ms) / len(prep_ms), 4),
                      "alg_bytes_per_launch": alg_bytes},
     }
 
@@ -190,6 +208,9 @@ def batched_uneven(torch, I, mtgp):
     out = torch.empty(tot, dtype=torch.int32, device="cuda")
     base = out.data_ptr()
     rq = [(r.gen, r.kind, r.n, base + 4 * r.offset) for r in reqs]
+    t0 = time.perf_counter()
+    tuning = batch.autotune(rq, reps=2)
+    tune_s = time.perf_counter() - t0
     plan = batch.plan(rq)
     ms_b = timed_ms(torch, lambda: plan.launch(), reps=3)
     torch.cuda.synchronize()
@@ -204,7 +225,8 @@ def batched_uneven(torch, I, mtgp):
     Ns = {11213: 351, 23209: 726, 44497: 1391}
     alg = sum(4 * r.n + 8 * Ns[params[r.gen].mexp] + 256 for r in reqs)
     return {"generators": G, "numbers": tot,
-            "batched": {"ms": round(ms_b, 3), "G_numbers_s": round(tot / ms_b / 1e6, 2), **roof(alg, ms_b / 1e3)},
+            "batched": {"ms": round(ms_b, 3), "G_numbers_s": round(tot / ms_b / 1e6, 2), **roof(alg, ms_b / 1e3),
+                        "autotuned": tuning, "autotune_s": round(tune_s, 1)},
             "plain_one_launch_per_request": {"ms": round(ms_p, 1), "G_numbers_s": round(tot / ms_p / 1e6, 3)},
             "speedup_batched_vs_plain": round(ms_p / ms_b, 1)}
 
@@ -216,7 +238,11 @@ def large_states(torch, I, mtgp):
         G = len(params)
         batch = mtgp.Batch(params, I.state_seeds(G))
         out = torch.empty(G * n, dtype=torch.int32, device="cuda")
-        plan = batch.plan([(g, 0, n, out.data_ptr() + 4 * g * n) for g in range(G)])
+        rq = [(g, 0, n, out.data_ptr() + 4 * g * n) for g in range(G)]
+        t0 = time.perf_counter()
+        tuning = batch.autotune(rq, reps=2)
+        tune_s = time.perf_counter() - t0
+        plan = batch.plan(rq)
         ms = timed_ms(torch, lambda: plan.launch(), reps=3)
         plan.close()
         batch.close()
@@ -224,7 +250,8 @@ def large_states(torch, I, mtgp):
         torch.cuda.empty_cache()
         alg = G * (4 * n + 8 * N + 256)
         res[f"p{mexp}"] = {"generators": G, "numbers": G * n, "ms": round(ms, 3),
-                           "G_numbers_s": round(G * n / ms / 1e6, 2), **roof(alg, ms / 1e3)}
+                           "G_numbers_s": round(G * n / ms / 1e6, 2), **roof(alg, ms / 1e3),
+                           "autotuned": tuning, "autotune_s": round(tune_s, 1)}
     return res
 
 
@@ -282,7 +309,7 @@ def main():
     from paper_1005_4973_amd import mtgp
 
     torch.cuda.set_device(0)
-    params, n, kinds, head = headline(args, torch, I, mtgp)
+    params, n, kinds, tuning, head = headline(args, torch, I, mtgp)
     log(f"headline: {head['value']} G numbers/s")
 
     res = {
@@ -300,9 +327,10 @@ def main():
         "data": "synthetic (seeded parameter sets and states)",
         "config": {"workload": "128 independent MTGP-11213 generators (distinct seeded parameter sets, "
                                "M in [2,95]), 2^22 outputs each as uint32, float32 [1,2) and float32 [0,1); "
-                               "one graph-captured persistent launch per output kind",
+                               "one graph-captured plan per output kind (jump-ahead segment states, then "
+                               "persistent generation)",
                    "generators": 128, "mexp": 11213, "outputs_per_generator": n,
-                   "kinds": ["uint32", "float32_1to2", "float32_0to1"]},
+                   "kinds": ["uint32", "float32_1to2", "float32_0to1"], "autotuned": tuning},
         "roofline": head["roofline"],
     }
     if not args.no_cpu_baseline:

@@ -180,7 +180,45 @@ typedef struct mtgp_plan mtgp_plan_t;
 int mtgp_batch_set_split(mtgp_batch_t *b, uint32_t max_rounds);
 mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq);
 int mtgp_plan_launch(mtgp_plan_t *p, void *stream);
+
+/*
+ * One phase of a plan launch, for callers that time or overlap the phases.
+ * MTGP_PHASE_PREPARE computes the start states of the segments (the raw
+ * prefix and jump kernels; nothing for a plan without segments);
+ * MTGP_PHASE_GENERATE runs the persistent generation and advances the
+ * generators. A replay is PREPARE then GENERATE, stream-ordered, each once;
+ * MTGP_PHASE_ALL (what mtgp_plan_launch does) is both in one graph launch.
+ * Returns MTGP_EINVAL for an unknown phase or a stale plan.
+ */
+#define MTGP_PHASE_ALL 0
+#define MTGP_PHASE_PREPARE 1
+#define MTGP_PHASE_GENERATE 2
+int mtgp_plan_launch_phase(mtgp_plan_t *p, int phase, void *stream);
 void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's last stream */
+
+/*
+ * Autotuner for a request list (unique generators, as for plans). Times `reps`
+ * plan launches on `stream` for each candidate configuration -- the automatic
+ * launch shape with no split and with split limits halving from the longest
+ * request's round count down to 128 rounds, then, at the best split limit,
+ * workgroup forms of 128/256/512 lanes with 1-4 steps per lane and the
+ * wavefront form -- and keeps the fastest as the batch's launch shape
+ * (mtgp_batch_set_launch) and split limit (mtgp_batch_set_split). Outputs are
+ * identical under every configuration; the generators' states and counters
+ * are restored after each trial, so the call leaves the streams where they
+ * were. The request outputs are overwritten. The result is written to *best
+ * if non-NULL: mode -1 (threads, spl 0) means the automatic shape. Returns
+ * MTGP_EINVAL for bad requests or reps == 0, MTGP_ENOMEM, or MTGP_EDEVICE (the
+ * previous settings are then kept).
+ */
+typedef struct {
+    int mode, threads, spl;   /* chosen shape; mode -1: the automatic shape */
+    uint32_t split_rounds;    /* chosen split limit (0: no split) */
+    float ms;                 /* its mean plan launch time */
+    uint32_t trials;          /* configurations timed */
+} mtgp_tuning;
+int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream, uint32_t reps,
+                        mtgp_tuning *best);
 
 /* ---------------------------------------------------------------------------
  * Launch shape (for tuning; results are identical for every valid shape).

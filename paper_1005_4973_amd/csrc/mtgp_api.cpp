@@ -204,6 +204,7 @@ struct mtgp_batch {
     std::vector<uint64_t> consumed;
     GenRecord *d_recs = nullptr;
     uint32_t *d_states = nullptr;
+    size_t state_words = 0;        // words of d_states
     uint32_t *d_counters = nullptr;
     WorkItem *d_items = nullptr;
     WorkItem *h_items = nullptr;   // pinned staging for the item list
@@ -229,13 +230,19 @@ struct mtgp_plan {
     WorkItem *d_items = nullptr;
     uint32_t *d_counters = nullptr;
     hipStream_t capture = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // graphs: [0] both phases, [1] prepare only, [2] generate only
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     LaunchShape shape;
     // jump-ahead segments
     std::vector<uint32_t> split_gens;
     std::vector<uint64_t> split_epochs;
     void *d_jump_mem = nullptr;                // raw words, polynomials, segment states, prefix and jump items
+    WorkItem *d_prefix = nullptr;              // raw-prefix items (in d_items' allocation)
+    uint32_t nprefix = 0;
+    LaunchShape pshape;                        // launch shape of the raw prefix
+    JumpItem *d_jumps = nullptr;               // jump items (in d_items' allocation)
+    std::vector<JumpItem> jumps;               // host copy, grouped by lane width
 };
 
 namespace {
@@ -247,19 +254,20 @@ namespace {
 // LDS and the grid is k * CUs: the hardware then has to place k workgroups on
 // every CU. (Left free, it packed several latency-bound generators onto one
 // CU while others idled.) k = 1 gives each generator a whole CU.
-LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem> &items)
+LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, int threads = 256,
+                                int spl = 4)
 {
     LaunchShape s;
     s.mode = kModeGroup;
-    s.threads = 256;
-    s.spl = 4;
+    s.threads = threads;
+    s.spl = spl;
     s.grid = 1;
     uint32_t need = 0;
     for (const WorkItem &it : items)
         need = std::max(need, window_need(b->recs[it.gen], s));
     s.lds_words = 1;
     const uint32_t cap = max_window_words(s, b->max_lds);
-    const uint32_t by_waves = kWavesPerCu / (uint32_t)(s.threads / 64);
+    const uint32_t by_waves = std::max(1u, kWavesPerCu / (uint32_t)(s.threads / 64));
     const uint64_t cus = (uint64_t)b->cu_count;
     uint32_t k = (uint32_t)std::min<uint64_t>(by_waves, (items.size() + cus - 1) / cus);
     k = std::max(k, 1u);
@@ -276,7 +284,11 @@ LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem>
 int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, LaunchShape &out)
 {
     LaunchShape s;
-    if (b->have_override) {
+    if (b->have_override && b->override_shape.mode == kModeGroup && b->override_shape.lds_words == 0 &&
+        b->override_shape.grid == 0) {
+        // workgroup form with automatic window and grid: placed like the default
+        s = batch_default_shape(b, items, b->override_shape.threads, b->override_shape.spl);
+    } else if (b->have_override) {
         s = b->override_shape;
         if (s.lds_words == 0) {
             uint32_t need = 0;
@@ -371,16 +383,42 @@ void plan_free(mtgp_plan *p)
 {
     if (!p)
         return;
-    if (p->exec)
-        hipGraphExecDestroy(p->exec);
-    if (p->graph)
-        hipGraphDestroy(p->graph);
+    for (int k = 0; k < 3; k++) {
+        if (p->exec[k])
+            hipGraphExecDestroy(p->exec[k]);
+        if (p->graph[k])
+            hipGraphDestroy(p->graph[k]);
+    }
     if (p->capture)
         hipStreamDestroy(p->capture);
     hipFree(p->d_items);
     hipFree(p->d_counters);
     hipFree(p->d_jump_mem);
     delete p;
+}
+
+// Enqueue the kernels of a plan's phases (bit 0: raw prefix and jumps, bit 1:
+// generation) on the plan's capture stream and instantiate them as a graph.
+bool capture_phases(mtgp_plan *p, int mask, hipGraph_t &graph, hipGraphExec_t &exec)
+{
+    if (hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return false;
+    WorkItem none;
+    std::memset(&none, 0, sizeof(none));
+    const mtgp_batch *b = p->b;
+    hipError_t le = hipSuccess;
+    if ((mask & 1) && p->nprefix > 0) {
+        le = launch_generate(b->d_recs, b->d_states, p->d_prefix, p->nprefix, nullptr, none, p->pshape, p->capture);
+        if (le == hipSuccess)
+            le = launch_jumps(p->d_jumps, p->jumps.data(), (uint32_t)p->jumps.size(), p->capture);
+    }
+    if ((mask & 2) && le == hipSuccess)
+        le = launch_generate(b->d_recs, b->d_states, p->d_items, (uint32_t)p->items.size(), p->d_counters, none,
+                             p->shape, p->capture);
+    const hipError_t ce = hipStreamEndCapture(p->capture, &graph);
+    if (le != hipSuccess || ce != hipSuccess || graph == nullptr)
+        return false;
+    return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -888,7 +926,7 @@ mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds,
     b->cu_count = prop.multiProcessorCount;
     b->max_lds = device_max_lds();
     if (hipMalloc(&b->d_recs, count * sizeof(GenRecord)) != hipSuccess ||
-        hipMalloc(&b->d_states, off * sizeof(uint32_t)) != hipSuccess ||
+        (b->state_words = off, hipMalloc(&b->d_states, off * sizeof(uint32_t)) != hipSuccess) ||
         hipMalloc(&b->d_counters, 2 * sizeof(uint32_t)) != hipSuccess) {
         batch_free(b);
         fail(MTGP_ENOMEM);
@@ -1092,46 +1130,33 @@ mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, u
         return nullptr;
     }
     d_extra = reinterpret_cast<char *>(p->d_items + nitems);
-    WorkItem *d_prefix = reinterpret_cast<WorkItem *>(d_extra);
-    JumpItem *d_jumps = reinterpret_cast<JumpItem *>(d_extra + prefix.size() * sizeof(WorkItem));
+    p->d_prefix = reinterpret_cast<WorkItem *>(d_extra);
+    p->nprefix = (uint32_t)prefix.size();
+    p->d_jumps = reinterpret_cast<JumpItem *>(d_extra + prefix.size() * sizeof(WorkItem));
+    p->jumps = jumps;
     std::vector<uint32_t> pgens;
     for (const WorkItem &it : prefix)
         pgens.push_back(it.gen);
-    LaunchShape pshape;
     if (!prefix.empty()) {
-        pshape = raw_shape(b, pgens);
+        p->pshape = raw_shape(b, pgens);
         for (WorkItem &it : prefix)
-            it.spl = item_spl(b->recs[it.gen].N, b->recs[it.gen].M, pshape);
+            it.spl = item_spl(b->recs[it.gen].N, b->recs[it.gen].M, p->pshape);
     }
     if (hipMemcpy(p->d_items, p->items.data(), nitems * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess ||
         (!prefix.empty() &&
-         hipMemcpy(d_prefix, prefix.data(), prefix.size() * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess) ||
+         hipMemcpy(p->d_prefix, prefix.data(), prefix.size() * sizeof(WorkItem), hipMemcpyHostToDevice) != hipSuccess) ||
         (!jumps.empty() &&
-         hipMemcpy(d_jumps, jumps.data(), jumps.size() * sizeof(JumpItem), hipMemcpyHostToDevice) != hipSuccess) ||
+         hipMemcpy(p->d_jumps, jumps.data(), jumps.size() * sizeof(JumpItem), hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemset(p->d_counters, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
         hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
         plan_free(p);
         fail(MTGP_EDEVICE);
         return nullptr;
     }
-    WorkItem none;
-    std::memset(&none, 0, sizeof(none));
-    bool ok = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    if (ok) {
-        hipError_t le = hipSuccess;
-        if (!prefix.empty())
-            le = launch_generate(b->d_recs, b->d_states, d_prefix, (uint32_t)prefix.size(), nullptr, none, pshape,
-                                 p->capture);
-        if (le == hipSuccess)
-            le = launch_jumps(d_jumps, jumps.data(), (uint32_t)jumps.size(), p->capture);
-        if (le == hipSuccess)
-            le = launch_generate(b->d_recs, b->d_states, p->d_items, nitems, p->d_counters, none, p->shape,
-                                 p->capture);
-        const hipError_t ce = hipStreamEndCapture(p->capture, &p->graph);
-        ok = le == hipSuccess && ce == hipSuccess && p->graph != nullptr;
-    }
-    if (ok)
-        ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+    bool ok = true;
+    for (int k = 0; k < 3 && ok; k++)
+        if (k != MTGP_PHASE_PREPARE || p->nprefix > 0)   // an unsplit plan has nothing to prepare
+            ok = capture_phases(p, k == MTGP_PHASE_ALL ? 3 : k, p->graph[k], p->exec[k]);
     if (!ok) {
         plan_free(p);
         fail(MTGP_EDEVICE);
@@ -1142,16 +1167,22 @@ mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, u
 
 int mtgp_plan_launch(mtgp_plan_t *p, void *stream)
 {
-    if (!p)
+    return mtgp_plan_launch_phase(p, MTGP_PHASE_ALL, stream);
+}
+
+int mtgp_plan_launch_phase(mtgp_plan_t *p, int phase, void *stream)
+{
+    if (!p || phase < MTGP_PHASE_ALL || phase > MTGP_PHASE_GENERATE)
         return fail(MTGP_EINVAL);
     for (size_t i = 0; i < p->split_gens.size(); i++)
         if (p->b->epoch[p->split_gens[i]] != p->split_epochs[i])
             return fail(MTGP_EINVAL);   // a split generator's state was replaced: the plan is stale
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (hipGraphLaunch(p->exec, s) != hipSuccess)
+    if (p->exec[phase] && hipGraphLaunch(p->exec[phase], s) != hipSuccess)
         return fail(MTGP_EDEVICE);
-    for (const WorkItem &it : p->items)
-        p->b->consumed[it.gen] += it.n;
+    if (phase != MTGP_PHASE_PREPARE)
+        for (const WorkItem &it : p->items)
+            p->b->consumed[it.gen] += it.n;
     p->b->last = s;
     return MTGP_OK;
 }
@@ -1163,6 +1194,135 @@ void mtgp_plan_destroy(mtgp_plan_t *p)
     if (p->b)
         hipStreamSynchronize(p->b->last);
     plan_free(p);
+}
+
+int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream, uint32_t reps,
+                        mtgp_tuning *best)
+{
+    if (!b || nreq == 0 || reps == 0 || validate_requests(b, reqs, nreq, true) != MTGP_OK)
+        return fail(MTGP_EINVAL);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the generators' states and counters, restored after every trial
+    uint32_t *d_save = nullptr;
+    if (hipStreamSynchronize(b->last) != hipSuccess)
+        return fail(MTGP_EDEVICE);
+    if (hipMalloc(&d_save, b->state_words * sizeof(uint32_t)) != hipSuccess)
+        return fail(MTGP_ENOMEM);
+    if (hipMemcpy(d_save, b->d_states, b->state_words * sizeof(uint32_t), hipMemcpyDeviceToDevice) != hipSuccess) {
+        hipFree(d_save);
+        return fail(MTGP_EDEVICE);
+    }
+    const std::vector<uint64_t> consumed = b->consumed;
+    const bool had_override = b->have_override;
+    const LaunchShape had_shape = b->override_shape;
+    const uint32_t had_split = b->split_rounds;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        hipFree(d_save);
+        return fail(MTGP_EDEVICE);
+    }
+
+    struct Cand {
+        bool automatic;
+        LaunchShape shape;
+        uint32_t split;
+        float ms;
+    };
+    // mean launch time of one configuration, or a negative value if its plan
+    // cannot be built
+    bool device_ok = true;
+    auto trial = [&](Cand &c) {
+        b->have_override = !c.automatic;
+        b->override_shape = c.shape;
+        b->split_rounds = c.split;
+        c.ms = -1.0f;
+        mtgp_plan *p = mtgp_batch_plan_create(b, reqs, nreq);
+        if (!p)
+            return;
+        bool ok = mtgp_plan_launch(p, s) == MTGP_OK && hipEventRecord(e0, s) == hipSuccess;
+        for (uint32_t r = 0; ok && r < reps; r++)
+            ok = mtgp_plan_launch(p, s) == MTGP_OK;
+        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            c.ms = ms / (float)reps;
+        device_ok = device_ok && ok;
+        mtgp_plan_destroy(p);
+        device_ok = device_ok &&
+                    hipMemcpyAsync(b->d_states, d_save, b->state_words * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                   s) == hipSuccess &&
+                    hipStreamSynchronize(s) == hipSuccess;
+        b->consumed = consumed;
+    };
+
+    // split limits: none, then halving from the longest request's rounds
+    std::vector<WorkItem> items = items_of(reqs, nreq);
+    LaunchShape ds = batch_default_shape(b, items);
+    uint64_t rmax = 0;
+    for (const WorkItem &it : items) {
+        const GenRecord &r = b->recs[it.gen];
+        const uint32_t W = round_width(r.N, r.M, ds);
+        rmax = std::max<uint64_t>(rmax, (it.n + W - 1) / W);
+    }
+    std::vector<Cand> tried;
+    Cand c0{true, had_shape, 0, 0.0f};
+    trial(c0);
+    tried.push_back(c0);
+    for (uint64_t sr = rmax / 2; sr >= 128 && tried.size() < 8 && device_ok; sr /= 2) {
+        Cand c{true, had_shape, (uint32_t)sr, 0.0f};
+        trial(c);
+        tried.push_back(c);
+    }
+    auto best_of = [&]() {
+        size_t k = 0;
+        for (size_t i = 0; i < tried.size(); i++)
+            if (tried[i].ms > 0 && (tried[k].ms <= 0 || tried[i].ms < tried[k].ms))
+                k = i;
+        return tried[k];
+    };
+    // launch shapes at the best split limit
+    const uint32_t split = best_of().split;
+    const int shapes[][3] = {{kModeGroup, 256, 1}, {kModeGroup, 256, 2}, {kModeGroup, 512, 1},
+                             {kModeGroup, 128, 4}, {kModeWave, 256, 8}};
+    for (const auto &sh : shapes) {
+        if (!device_ok)
+            break;
+        Cand c{false, LaunchShape{}, split, 0.0f};
+        c.shape.mode = sh[0];
+        c.shape.threads = sh[1];
+        c.shape.spl = sh[2];
+        c.shape.lds_words = 0;
+        c.shape.grid = 0;
+        LaunchShape probe = c.shape;
+        probe.lds_words = 1;
+        probe.grid = 1;
+        if (!shape_valid(probe, b->max_lds))
+            continue;
+        trial(c);
+        tried.push_back(c);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(d_save);
+    const Cand win = best_of();
+    if (!device_ok || win.ms <= 0) {
+        b->have_override = had_override;
+        b->override_shape = had_shape;
+        b->split_rounds = had_split;
+        return fail(device_ok ? MTGP_EINVAL : MTGP_EDEVICE);
+    }
+    b->have_override = !win.automatic;
+    b->override_shape = win.shape;
+    b->split_rounds = win.split;
+    if (best) {
+        best->mode = win.automatic ? -1 : win.shape.mode;
+        best->threads = win.automatic ? 0 : win.shape.threads;
+        best->spl = win.automatic ? 0 : win.shape.spl;
+        best->split_rounds = win.split;
+        best->ms = win.ms;
+        best->trials = (uint32_t)tried.size();
+    }
+    return MTGP_OK;
 }
 
 }  // extern "C"

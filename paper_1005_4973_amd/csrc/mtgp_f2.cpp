@@ -198,46 +198,51 @@ Poly powmod_x(uint64_t e, const Poly &m)
 Poly minpoly(const uint64_t *bits, int64_t n)
 {
     // Work on the reversed sequence, so that s_j, s_{j-1}, ..., s_{j-L} is a
-    // forward run of bits starting at reversed position n-1-j.
+    // forward run of bits starting at reversed position n-1-j. The reversed
+    // sequence is kept in 64 copies shifted by 0..63 bits, so the run at any
+    // position is read as aligned words and the discrepancy is a tight
+    // AND/XOR loop.
     const size_t nw = (size_t)(n / 64 + 4);
-    std::vector<uint64_t> rs(nw, 0);
+    std::vector<uint64_t> rs(nw + 1, 0);
     for (int64_t j = 0; j < n; j++)
         if ((bits[j >> 6] >> (j & 63)) & 1)
             rs[(size_t)((n - 1 - j) >> 6)] |= 1ull << ((n - 1 - j) & 63);
-    auto window = [&](int64_t pos) -> uint64_t {
-        const size_t wi = (size_t)(pos >> 6);
-        const int b = (int)(pos & 63);
-        const uint64_t lo = wi < nw ? rs[wi] : 0;
-        const uint64_t hi = wi + 1 < nw ? rs[wi + 1] : 0;
-        return b ? (lo >> b) | (hi << (64 - b)) : lo;
-    };
-    // C: connection polynomial (c_0 = 1), B: the one before the last length
-    // change; deg(x^m B) <= n always, so only B's low (n - m)/64 + 2 words can
-    // be non-zero, and C needs n/64 + 4 words.
-    std::vector<uint64_t> C(nw, 0), B(nw, 0), T;
+    std::vector<uint64_t> shifted(64 * nw);   // shifted[s * nw + k] = bits [64k + s, 64k + s + 64)
+    for (int sft = 0; sft < 64; sft++)
+        for (size_t k = 0; k < nw; k++)
+            shifted[(size_t)sft * nw + k] = sft ? (rs[k] >> sft) | (rs[k + 1] << (64 - sft)) : rs[k];
+    // C: connection polynomial (c_0 = 1) of degree <= L; B: the one before the
+    // last length change, of degree <= LB (the length then). C needs n/64 + 4
+    // words; only the low LB/64 + 1 words of B can be non-zero.
+    std::vector<uint64_t> C(nw, 0), B(nw, 0), T(nw, 0);
     C[0] = 1;
     B[0] = 1;
-    int64_t L = 0, m = 1;
+    int64_t L = 0, LB = 0, m = 1;
     auto add_shifted_B = [&]() {
-        const size_t nb = std::min(nw - (size_t)(m >> 6) - 1, (size_t)((n - m) / 64 + 2));
+        const size_t nb = std::min(nw - (size_t)(m >> 6) - 1, (size_t)(LB / 64 + 1));
         xor_shl(C.data(), B.data(), nb, m);
     };
     for (int64_t j = 0; j < n; j++) {
-        uint64_t acc = 0;
         const int64_t base = n - 1 - j;
-        for (int64_t i = 0; i <= L; i += 64) {
-            uint64_t cw = C[(size_t)(i >> 6)];
-            if (L - i < 63)
-                cw &= ((1ull << (L - i + 1)) - 1);
-            acc ^= cw & window(base + i);
-        }
+        const uint64_t *run = shifted.data() + (size_t)(base & 63) * nw + (size_t)(base >> 6);
+        const size_t full = (size_t)(L / 64);   // words of C below the last, partial one
+        uint64_t acc = 0;
+        for (size_t w = 0; w < full; w++)
+            acc ^= C[w] & run[w];
+        const int top = (int)(L - (int64_t)full * 64);   // bits 0 .. top of the last word
+        const uint64_t last = top == 63 ? ~0ull : ((1ull << (top + 1)) - 1);
+        acc ^= C[full] & last & run[full];
         if (!__builtin_parityll(acc)) {
             m++;
         } else if (2 * L <= j) {
-            T = C;
+            // B <- C (its low L/64 + 1 words hold all of it), C <- C + x^m B
+            const size_t cw = (size_t)(L / 64 + 1);
+            std::copy(C.begin(), C.begin() + (ptrdiff_t)cw, T.begin());
             add_shifted_B();
+            std::fill(B.begin(), B.begin() + (ptrdiff_t)(LB / 64 + 1), 0);
+            std::copy(T.begin(), T.begin() + (ptrdiff_t)cw, B.begin());
+            LB = L;
             L = j + 1 - L;
-            B = T;
             m = 1;
         } else {
             add_shifted_B();

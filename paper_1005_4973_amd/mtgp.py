@@ -20,6 +20,10 @@ MTGP_EINVAL = -1
 MTGP_ENOMEM = -2
 MTGP_EDEVICE = -3
 
+PHASE_ALL = 0
+PHASE_PREPARE = 1
+PHASE_GENERATE = 2
+
 KIND_UINT32 = 0
 KIND_FLOAT32_1TO2 = 1
 KIND_FLOAT32_0TO1 = 2
@@ -35,6 +39,11 @@ class ParamSetC(ctypes.Structure):
     _fields_ = [("mexp", ctypes.c_uint32), ("pos", ctypes.c_uint32),
                 ("sh1", ctypes.c_uint32), ("sh2", ctypes.c_uint32),
                 ("param_tbl", ctypes.c_uint32 * 16), ("temper_tbl", ctypes.c_uint32 * 16)]
+
+
+class TuningC(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("threads", ctypes.c_int), ("spl", ctypes.c_int),
+                ("split_rounds", ctypes.c_uint32), ("ms", ctypes.c_float), ("trials", ctypes.c_uint32)]
 
 
 class RequestC(ctypes.Structure):
@@ -71,7 +80,10 @@ _SIGNATURES = {
     "mtgp_batch_destroy": (None, [ctypes.c_void_p]),
     "mtgp_batch_plan_create": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32]),
     "mtgp_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_plan_launch_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "mtgp_batch_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.c_uint32, ctypes.POINTER(TuningC)]),
     "mtgp_plan_destroy": (None, [ctypes.c_void_p]),
     "mtgp_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 5),
     "mtgp_set_launch": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 4),
@@ -247,6 +259,16 @@ class Batch:
         """Split plan requests longer than max_rounds rounds into jump-ahead segments (0: off)."""
         _check(lib().mtgp_batch_set_split(self._h, max_rounds), "mtgp_batch_set_split")
 
+    def autotune(self, requests: Iterable, reps: int = 5, stream: Optional[torch.cuda.Stream] = None) -> dict:
+        """Time candidate launch shapes and split limits on these requests and keep
+        the fastest (mtgp_batch_autotune); streams are left where they were."""
+        arr, k = Batch._reqs(requests)
+        t = TuningC()
+        _check(lib().mtgp_batch_autotune(self._h, arr, k, _stream_ptr(stream), reps, ctypes.byref(t)),
+               "mtgp_batch_autotune")
+        return {"mode": t.mode, "threads": t.threads, "spl": t.spl, "split_rounds": t.split_rounds,
+                "ms": round(t.ms, 4), "trials": t.trials}
+
     def plan(self, requests: Iterable) -> "Plan":
         """Capture the persistent launch for a fixed request list (see Plan)."""
         return Plan(self, requests)
@@ -293,6 +315,11 @@ class Plan:
 
     def launch(self, stream: Optional[torch.cuda.Stream] = None):
         _check(lib().mtgp_plan_launch(self._h, _stream_ptr(stream)), "mtgp_plan_launch")
+
+    def launch_phase(self, phase: int, stream: Optional[torch.cuda.Stream] = None):
+        """PHASE_PREPARE (segment start states) or PHASE_GENERATE; a replay is
+        both, in that order (mtgp_plan_launch_phase)."""
+        _check(lib().mtgp_plan_launch_phase(self._h, int(phase), _stream_ptr(stream)), "mtgp_plan_launch_phase")
 
     def close(self):
         if getattr(self, "_h", None):

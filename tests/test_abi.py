@@ -50,6 +50,11 @@ def test_host_only_calls():
     assert L.mtgp_strerror(-1) == b"invalid argument or parameter set"
     L.mtgp_destroy(None)
     L.mtgp_batch_destroy(None)
+    L.mtgp_plan_destroy(None)
+    # NULL handles are rejected before any device work
+    assert L.mtgp_plan_launch_phase(None, mtgp.PHASE_GENERATE, None) == mtgp.MTGP_EINVAL
+    assert L.mtgp_batch_autotune(None, None, 1, None, 3, None) == mtgp.MTGP_EINVAL
+    assert L.mtgp_batch_set_split(None, 8) == mtgp.MTGP_EINVAL
 
 
 def test_create_rejects_bad_parameters_before_touching_the_device():

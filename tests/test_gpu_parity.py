@@ -336,3 +336,64 @@ def test_plan_split_jump_ahead(M):
         plan.launch()
     plan.close()
     b.close()
+
+
+def test_plan_phases(M):
+    """PREPARE then GENERATE equals a whole launch, split or not."""
+    import torch
+    params = I.draw_param_sets([11213] * 4 + [23209] * 2, 81)
+    seeds = I.state_seeds(len(params))
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    rng = I.SplitMix64(82)
+    reqs = [(g, g % 3, rng.uniform_int(20000, 60000)) for g in range(len(params))]
+    for split in (0, 8):
+        say(f"plan phases split={split}")
+        b = M.Batch(params, seeds)
+        b.set_split(split)
+        st = {g: v.copy() for g, v in states.items()}
+        bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+        plan = b.plan([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+        for rep in range(2):
+            plan.launch_phase(M.PHASE_PREPARE)
+            plan.launch_phase(M.PHASE_GENERATE)
+            torch.cuda.synchronize()
+            for (g, k, n), buf in zip(reqs, bufs):
+                np.testing.assert_array_equal(host_bits(buf), O.generate(params[g], st[g], n, k),
+                                              err_msg=f"split={split} rep={rep} gen={g}")
+        for g, (_, _, n) in enumerate(reqs):
+            words, consumed = b.get_state(g)
+            np.testing.assert_array_equal(words, st[g])
+            assert consumed == 2 * n
+        with pytest.raises(M.MTGPError):
+            plan.launch_phase(7)
+        plan.close()
+        b.close()
+
+
+def test_autotune_leaves_streams_and_keeps_parity(M):
+    import torch
+    params = I.draw_param_sets([11213] * 6 + [44497] * 2, 83)
+    seeds = I.state_seeds(len(params))
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    n = 1 << 17
+    out = torch.empty(len(params) * n, dtype=torch.int32, device="cuda")
+    reqs = [(g, g % 3, n, out.data_ptr() + 4 * g * n) for g in range(len(params))]
+    b = M.Batch(params, seeds)
+    say("autotune")
+    best = b.autotune(reqs, reps=2)
+    say(f"autotune chose {best}")
+    assert best["trials"] >= 2 and best["ms"] > 0
+    for g in range(len(params)):
+        words, consumed = b.get_state(g)
+        np.testing.assert_array_equal(words, states[g])
+        assert consumed == 0
+    plan = b.plan(reqs)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        host = host_bits(out)
+        for g in range(len(params)):
+            np.testing.assert_array_equal(host[g * n:(g + 1) * n], O.generate(params[g], states[g], n, g % 3),
+                                          err_msg=f"rep={rep} gen={g}")
+    plan.close()
+    b.close()
