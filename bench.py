@@ -107,10 +107,13 @@ def measured_traffic(tuning):
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
     fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:", "split_rounds:")))
+                  if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:", "tuning:")))
     if fields.get("kernel_source_sha256_16", "").split()[0:1] != [h.hexdigest()[:16]]:
         return None
-    if fields.get("split_rounds", "").strip() != str(tuning["split_rounds"]):
+    # the split limit sets the segments whose start states the kernel reads;
+    # the launch shape changes no byte the kernel moves
+    recorded = dict(kv.split("=") for kv in fields.get("tuning", "").split())
+    if recorded.get("split_rounds") != str(tuning["split_rounds"]):
         return None
     return int(fields["traffic_bytes_per_launch"].strip())
 

@@ -202,7 +202,8 @@ void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's la
  * launch shape with no split and with split limits halving from the longest
  * request's round count down to 128 rounds, then, at the best split limit,
  * workgroup forms of 128/256/512 lanes with 1-4 steps per lane and the
- * wavefront form -- and keeps the fastest as the batch's launch shape
+ * wavefront form -- and keeps the fastest (a later candidate must be at least
+ * 2 % faster than the one it replaces) as the batch's launch shape
  * (mtgp_batch_set_launch) and split limit (mtgp_batch_set_split). Outputs are
  * identical under every configuration; the generators' states and counters
  * are restored after each trial, so the call leaves the streams where they
