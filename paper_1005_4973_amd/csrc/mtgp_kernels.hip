@@ -79,9 +79,19 @@ __device__ __forceinline__ uint32_t output_word(uint32_t x, uint32_t tv)
 constexpr int kBufferWord3 = 0x00020000;
 constexpr int kStoreNT = 2;
 
+// The window is the same for every lane of a wavefront; readfirstlane keeps
+// the descriptor in scalar registers (a descriptor in vector registers makes
+// every store a loop over the lanes' distinct descriptors).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_window(gu32 *p, uint32_t cnt)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(static_cast<void *>(p), 0, (int)(cnt * 4u), kBufferWord3);
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    // readfirstlane returns int: take each half as uint32_t, so the low half
+    // is zero-extended (sign extension would corrupt the address)
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    gu32 *q = reinterpret_cast<gu32 *>(((uint64_t)hi << 32) | lo);
+    const uint32_t bytes = __builtin_amdgcn_readfirstlane(cnt * 4u);
+    return __builtin_amdgcn_make_buffer_rsrc(static_cast<void *>(q), 0, (int)bytes, kBufferWord3);
 }
 
 // One round: SPL step slots per lane, slot c of lane `lane` is step
@@ -257,7 +267,11 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
     extern __shared__ uint32_t smem[];
     const uint32_t lane = WAVE ? (threadIdx.x & 63u) : threadIdx.x;
     const uint32_t T = WAVE ? 64u : blockDim.x;
-    const uint32_t unit = WAVE ? (threadIdx.x >> 6) : 0u;
+    // the unit index is the same in every lane of a wavefront; readfirstlane
+    // tells the compiler so, keeping the unit's item, window and output
+    // descriptor in scalar registers (else each buffer store becomes a loop
+    // over the lanes' descriptors)
+    const uint32_t unit = WAVE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0u;
     const uint32_t units = WAVE ? (blockDim.x >> 6) : 1u;
     uint32_t *unit_lds = smem + unit * (kTableWords + L);
     uint32_t *otb = unit_lds + 16;

@@ -240,6 +240,36 @@ def test_launch_shapes_parity(M):
     b.close()
 
 
+def test_outputs_at_addresses_with_bit31_set(M):
+    """Output windows whose device address has bit 31 of its low word set, in
+    both launch forms (regression: the low half of the address must be
+    zero-extended when it is made wave-uniform)."""
+    import torch
+    params = I.draw_param_sets([11213] * 3 + [23209], 65)
+    seeds = I.state_seeds(len(params))
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    n = 5000
+    need = 4 * n * len(params)
+    big = torch.empty((1 << 29) + (1 << 22), dtype=torch.int32, device="cuda")   # 2 GiB + 16 MiB
+    base = big.data_ptr()
+    off = 0 if (base >> 31) & 1 else (1 << 31) - (base & 0x7FFFFFFF)
+    off = (off + 255) & ~255
+    assert off + need <= big.numel() * 4 and ((base + off) >> 31) & 1
+    b = M.Batch(params, seeds)
+    for sh in [(0, 256, 4, 0, 0), (1, 256, 4, 0, 0)]:
+        say(f"bit-31 outputs, shape {sh}")
+        b.set_launch(*sh)
+        b.generate([(g, g % 3, n, base + off + 4 * n * g) for g in range(len(params))])
+        torch.cuda.synchronize()
+        host = host_bits(big[off // 4: off // 4 + n * len(params)])
+        for g in range(len(params)):
+            np.testing.assert_array_equal(host[g * n:(g + 1) * n], O.generate(params[g], states[g], n, g % 3),
+                                          err_msg=f"shape={sh} gen={g}")
+    b.close()
+    del big
+    torch.cuda.empty_cache()
+
+
 def test_single_generator_shapes(M):
     (ps,), _ = I.single_stream()
     st = O.seed_state(21, ps.mexp)
