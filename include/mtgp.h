@@ -49,6 +49,15 @@ extern "C" {
 #define MTGP_KIND_UINT32        0   /* tempered 32-bit word o_{N+k} */
 #define MTGP_KIND_FLOAT32_1TO2  1   /* bits 0x3f800000 | (o >> 9): float in [1,2) */
 #define MTGP_KIND_FLOAT32_0TO1  2   /* the [1,2) value minus 1.0f: float in [0,1) */
+/* Gaussian float32 by the Box-Muller transform of float [1,2) outputs, which
+ * section 6 names as a direct use of that range: for the pair (a, b) of
+ * [1,2) values at positions 2j, 2j+1 counted from the start of the call or
+ * request, r = sqrt(-2 ln(2 - a)); output 2j = r cos(2 pi (b - 1)) and
+ * output 2j+1 = r sin(2 pi (b - 1)). n outputs consume n steps. Requires an
+ * even n and N - M >= 2 (MTGP_EINVAL otherwise). Computed in binary32 with
+ * the device's logf, sqrtf and sincospif: not bit-exact against a
+ * reference, within a few units in the last place. */
+#define MTGP_KIND_NORMAL_FLOAT32 3
 
 /*
  * Parameter set (section 3.6 and 3.7). Copied at create time; the caller
@@ -97,6 +106,7 @@ mtgp_t *mtgp_create(const mtgp_param_set *ps, uint32_t seed);
 int mtgp_generate_uint32(mtgp_t *g, size_t n, uint32_t *out, void *stream);
 int mtgp_generate_float32_1to2(mtgp_t *g, size_t n, float *out, void *stream);
 int mtgp_generate_float32_0to1(mtgp_t *g, size_t n, float *out, void *stream);
+int mtgp_generate_normal_float32(mtgp_t *g, size_t n, float *out, void *stream);   /* n even */
 
 /* Release the handle (NULL-safe); waits for work queued on its last stream. */
 void mtgp_destroy(mtgp_t *g);

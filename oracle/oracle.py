@@ -97,6 +97,33 @@ def generate(ps, state: np.ndarray, n: int, kind: int = U32) -> np.ndarray:
     return out[:n]
 
 
+def normals_from_f12(f12_bits: np.ndarray) -> np.ndarray:
+    """Gaussian deviates by the Box-Muller transform, in float64, of
+    consecutive pairs of float [1,2) outputs given as bit patterns.
+
+    Section 6 of the paper notes that the [1,2) outputs serve the Box-Muller
+    transformation directly. Reading taken: for the pair (a, b) at positions
+    2j, 2j+1, u1 = 2 - a lies in (0, 1] and u2 = b - 1 in [0, 1);
+    r = sqrt(-2 ln u1), theta = 2 pi u2; output 2j = r cos(theta),
+    output 2j+1 = r sin(theta). The pair count must be whole.
+    """
+    f = np.asarray(f12_bits, dtype=np.uint32).view(np.float32).astype(np.float64)
+    assert f.size % 2 == 0, "normals come in pairs"
+    a, b = f[0::2], f[1::2]
+    r = np.sqrt(-2.0 * np.log(2.0 - a))
+    theta = 2.0 * np.pi * (b - 1.0)
+    out = np.empty(f.size, dtype=np.float64)
+    out[0::2] = r * np.cos(theta)
+    out[1::2] = r * np.sin(theta)
+    return out
+
+
+def normals(ps, state: np.ndarray, n: int) -> np.ndarray:
+    """n Gaussian deviates (n even) from the float [1,2) stream; `state` is
+    advanced by n steps, as for the other kinds."""
+    return normals_from_f12(generate(ps, state, n, F12))
+
+
 def advance(ps, state: np.ndarray, n: int) -> None:
     rc = lib().orc_advance(ctypes.byref(to_c(ps)), state.ctypes.data, n)
     if rc != 0:

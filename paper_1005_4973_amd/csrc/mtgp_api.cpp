@@ -313,6 +313,9 @@ int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, Launc
     return MTGP_OK;
 }
 
+// Normals come in pairs within a call, and a round must hold whole pairs.
+bool normal_ok(const GenRecord &r, uint64_t n) { return n % 2 == 0 && r.N - r.M >= 2; }
+
 int validate_requests(const mtgp_batch *b, const mtgp_request *reqs, uint32_t nreq, bool unique)
 {
     if (!b || (nreq > 0 && !reqs))
@@ -320,7 +323,9 @@ int validate_requests(const mtgp_batch *b, const mtgp_request *reqs, uint32_t nr
     std::vector<uint8_t> seen(unique ? b->count : 0, 0);
     for (uint32_t i = 0; i < nreq; i++) {
         const mtgp_request &r = reqs[i];
-        if (r.gen >= b->count || r.kind > 2 || check_out(r.out, r.n) != MTGP_OK)
+        if (r.gen >= b->count || r.kind > MTGP_KIND_NORMAL_FLOAT32 || check_out(r.out, r.n) != MTGP_OK)
+            return MTGP_EINVAL;
+        if (r.kind == MTGP_KIND_NORMAL_FLOAT32 && !normal_ok(b->recs[r.gen], r.n))
             return MTGP_EINVAL;
         if (unique && r.n > 0) {
             if (seen[r.gen])
@@ -604,11 +609,13 @@ int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem>
         const uint64_t rounds = (items[i].n + w - 1) / w;
         if (rounds <= b->split_rounds)
             continue;
+        // J is even, so normals keep their pairs inside a segment
         uint32_t S = (uint32_t)((rounds + b->split_rounds - 1) / b->split_rounds);
-        uint64_t J = (items[i].n + S - 1) / S;
+        auto seg_len = [&](uint32_t s) { return ((items[i].n + s - 1) / s + 1) & ~(uint64_t)1; };
+        uint64_t J = seg_len(S);
         while (S > 1 && (uint64_t)(S - 1) * J >= items[i].n) {
             S--;
-            J = (items[i].n + S - 1) / S;
+            J = seg_len(S);
         }
         if (S > 1)
             specs.push_back({i, items[i].gen, S, J});
@@ -791,6 +798,8 @@ static int generate_kind(mtgp_t *g, size_t n, void *out, void *stream, uint32_t 
         return fail(MTGP_EINVAL);
     if (check_out(out, n) != MTGP_OK)
         return fail(MTGP_EINVAL);
+    if (kind == MTGP_KIND_NORMAL_FLOAT32 && !normal_ok(g->rec, n))
+        return fail(MTGP_EINVAL);
     if (n == 0)
         return MTGP_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -821,6 +830,11 @@ int mtgp_generate_float32_1to2(mtgp_t *g, size_t n, float *out, void *stream)
 int mtgp_generate_float32_0to1(mtgp_t *g, size_t n, float *out, void *stream)
 {
     return generate_kind(g, n, out, stream, MTGP_KIND_FLOAT32_0TO1);
+}
+
+int mtgp_generate_normal_float32(mtgp_t *g, size_t n, float *out, void *stream)
+{
+    return generate_kind(g, n, out, stream, MTGP_KIND_NORMAL_FLOAT32);
 }
 
 void mtgp_destroy(mtgp_t *g)

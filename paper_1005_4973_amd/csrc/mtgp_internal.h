@@ -26,7 +26,8 @@ static_assert(sizeof(GenRecord) == 256, "GenRecord layout");
 constexpr uint16_t kKindU32 = 0;     // tempered uint32
 constexpr uint16_t kKindF12 = 1;     // float [1,2)
 constexpr uint16_t kKindF01 = 2;     // float [0,1)
-constexpr uint16_t kKindRaw = 3;     // untempered words: the N start words, then x_{c+N}, x_{c+N+1}, ...
+constexpr uint16_t kKindNormal = 3;  // Gaussian float by Box-Muller on pairs of float [1,2) outputs
+constexpr uint16_t kKindRaw = 4;     // untempered words: the N start words, then x_{c+N}, x_{c+N+1}, ...
 constexpr uint16_t kKeepState = 0x100;   // flag: do not write the end state back to the generator
 
 // One unit of work: n outputs of `kind` from generator `gen` into `out`,

@@ -41,6 +41,10 @@
 //   uint32:      o = x_{i+N} ^ tmp[s & 0xf]
 //   float [1,2): o = (x_{i+N} >> 9) ^ flt[s & 0xf]       (section 6, eq. (C))
 //   float [0,1): the [1,2) value minus 1.0f
+//   normal:      Box-Muller on the pair of float [1,2) outputs (a, b) at
+//                positions 2j, 2j+1 of the call: r = sqrt(-2 ln(2 - a)),
+//                output 2j = r cos(2 pi (b - 1)), output 2j+1 = r sin(...);
+//                section 6 names [1,2) as the input for this transform
 #include "mtgp_internal.h"
 
 namespace mtgp_impl {
@@ -56,18 +60,37 @@ typedef uint32_t gu32;
 template <int KIND>
 __device__ __forceinline__ uint32_t output_word(uint32_t x, uint32_t tv)
 {
-    if constexpr (KIND == 0) {
+    if constexpr (KIND == kKindU32) {
         return x ^ tv;
-    } else if constexpr (KIND == 3) {
+    } else if constexpr (KIND == kKindRaw) {
         return x;   // untempered word (input of the jump correlation)
     } else {
         const uint32_t b = (x >> 9) ^ tv;
-        if constexpr (KIND == 1) {
-            return b;
-        } else {
+        if constexpr (KIND == kKindF01) {
             return __float_as_uint(__uint_as_float(b) - 1.0f);
+        } else {
+            return b;   // float [1,2); the normal kind transforms it in pairs
         }
     }
+}
+
+// DPP control quad_perm(1,0,3,2): lanes 2m and 2m+1 exchange values.
+constexpr int kDppSwapPairs = 0xb1;
+
+// Box-Muller on the float [1,2) bits `f` of this lane and of its pair
+// partner (lane ^ 1); the even lane holds the first of the pair. 2 - a and
+// 2(b - 1) are exact in binary32, so ln's argument lies in (0, 1] and the
+// angle is a multiple of pi taken by sincospi without rounding 2 pi.
+__device__ __forceinline__ uint32_t box_muller(uint32_t f, uint32_t lane)
+{
+    const uint32_t p = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, kDppSwapPairs, 0xf, 0xf, true);
+    const bool odd = lane & 1u;
+    const float a = __uint_as_float(odd ? p : f);
+    const float b = __uint_as_float(odd ? f : p);
+    const float r = sqrtf(-2.0f * logf(2.0f - a));
+    float sn, cs;
+    sincospif(2.0f * (b - 1.0f), &sn, &cs);
+    return __float_as_uint(r * (odd ? sn : cs));
 }
 
 // Output stores go through a buffer resource covering exactly the round's
@@ -153,7 +176,10 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const Rec
 #pragma unroll
     for (int c = 0; c < SPL; ++c) {
         const uint32_t k = lane + c * T;
-        __builtin_amdgcn_raw_buffer_store_b32(output_word<KIND>(x[c], tv[c]), rsrc, (int)(k * 4u), 0, kStoreNT);
+        uint32_t o = output_word<KIND>(x[c], tv[c]);
+        if constexpr (KIND == kKindNormal)
+            o = box_muller(o, lane);   // steps k and k^1 are lanes lane and lane^1 (T is even)
+        __builtin_amdgcn_raw_buffer_store_b32(o, rsrc, (int)(k * 4u), 0, kStoreNT);
     }
 }
 
@@ -316,7 +342,11 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
         uint32_t *slot = states + g.state_off;
         const uint32_t *from = it.src ? reinterpret_cast<const uint32_t *>(it.src) : slot;
         uint32_t *state = (flags & kKeepState) ? nullptr : slot;
-        const uint32_t W = (N - M) < T * spl ? (N - M) : T * spl;
+        uint32_t W = (N - M) < T * spl ? (N - M) : T * spl;
+        if (kind == kKindNormal)
+            W &= ~1u;   // rounds of whole pairs (the host requires N - M >= 2 for this kind)
+        if (W == 0)
+            W = 1;      // never reached through the library; keeps the loop bounds finite
 
         for (uint32_t k = lane; k < N; k += T)
             X[k] = from[k];
@@ -334,13 +364,15 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             out += N;
         }
         if (kind == kKindU32)
-            run_item<0, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindU32, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindF12)
-            run_item<1, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindF12, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindF01)
-            run_item<2, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindF01, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+        else if (kind == kKindNormal)
+            run_item<kKindNormal, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
         else
-            run_item<3, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindRaw, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
         if (!WAVE)
             __syncthreads();   // the next item overwrites the window and tables
     }

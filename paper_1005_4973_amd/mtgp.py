@@ -27,6 +27,7 @@ PHASE_GENERATE = 2
 KIND_UINT32 = 0
 KIND_FLOAT32_1TO2 = 1
 KIND_FLOAT32_0TO1 = 2
+KIND_NORMAL_FLOAT32 = 3   # Box-Muller on pairs of float [1,2) outputs; n even
 
 
 class MTGPError(RuntimeError):
@@ -68,6 +69,7 @@ _SIGNATURES = {
     "mtgp_generate_uint32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
     "mtgp_generate_float32_1to2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
     "mtgp_generate_float32_0to1": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_generate_normal_float32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]),
     "mtgp_destroy": (None, [ctypes.c_void_p]),
     "mtgp_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "mtgp_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
@@ -139,9 +141,10 @@ def _check(rc: int, what: str):
         raise MTGPError(rc, what)
 
 
-_DTYPE = {KIND_UINT32: torch.int32, KIND_FLOAT32_1TO2: torch.float32, KIND_FLOAT32_0TO1: torch.float32}
+_DTYPE = {KIND_UINT32: torch.int32, KIND_FLOAT32_1TO2: torch.float32, KIND_FLOAT32_0TO1: torch.float32,
+          KIND_NORMAL_FLOAT32: torch.float32}
 _GEN_FN = {KIND_UINT32: "mtgp_generate_uint32", KIND_FLOAT32_1TO2: "mtgp_generate_float32_1to2",
-           KIND_FLOAT32_0TO1: "mtgp_generate_float32_0to1"}
+           KIND_FLOAT32_0TO1: "mtgp_generate_float32_0to1", KIND_NORMAL_FLOAT32: "mtgp_generate_normal_float32"}
 
 
 def _out_tensor(n: int, kind: int, out: Optional[torch.Tensor], device) -> torch.Tensor:
@@ -177,6 +180,9 @@ class Generator:
 
     def generate_float32_0to1(self, n, out=None, stream=None):
         return self.generate(n, KIND_FLOAT32_0TO1, out, stream)
+
+    def generate_normal_float32(self, n, out=None, stream=None):
+        return self.generate(n, KIND_NORMAL_FLOAT32, out, stream)
 
     def set_launch(self, mode: int = -1, threads: int = 0, spl: int = 1, lds_words: int = 0):
         """Override the launch shape (mode -1 restores the automatic choice)."""

@@ -201,7 +201,7 @@ def test_batch_rejects_bad_requests(M):
     with pytest.raises(M.MTGPError):
         b.generate([(9, 0, 8, buf)])                          # no such generator
     with pytest.raises(M.MTGPError):
-        b.generate([(1, 3, 8, buf)])                          # no such kind
+        b.generate([(1, 4, 8, buf)])                          # no such kind (3 is the normal kind)
     b.close()
 
 
@@ -426,4 +426,73 @@ def test_autotune_leaves_streams_and_keeps_parity(M):
             np.testing.assert_array_equal(host[g * n:(g + 1) * n], O.generate(params[g], states[g], n, g % 3),
                                           err_msg=f"rep={rep} gen={g}")
     plan.close()
+    b.close()
+
+
+# ---------------------------------------------------------------------------
+# Box-Muller normals. binary32 logf / sqrtf / sincospif on the device against
+# the float64 oracle: 2 - a and 2(b - 1) are exact, ln carries <= 2 ulp, the
+# square root <= 1 ulp, sincospi <= 2 ulp and the product 0.5 ulp, so
+# |z - z_ref| <= 5.65 * (2.4e-7 + 2.4e-7) + 0.5 ulp(z) ~= 3e-6 (r <= 5.65).
+# The tolerance below keeps a factor of five over that.
+# ---------------------------------------------------------------------------
+
+NORMAL_ATOL = 1.5e-5
+
+
+def host_f32(t):
+    return t.view(__import__("torch").float32).cpu().numpy().astype(np.float64)
+
+
+def test_normals_single_generator_and_continuation(M):
+    (ps,), _ = I.single_stream()
+    st = O.seed_state(31, ps.mexp)
+    g = M.Generator(ps, 31)
+    for n in (2, 20000, 2 * 7777):
+        z = g.generate(n, M.KIND_NORMAL_FLOAT32)
+        ref = O.normals(ps, st, n)
+        err = np.abs(host_f32(z) - ref).max()
+        say(f"normals n={n} max |err| = {err:.3g}")
+        assert err <= NORMAL_ATOL
+    # the position advanced by exactly n per call: integer outputs continue bit-exactly
+    out = g.generate(9999, M.KIND_UINT32)
+    np.testing.assert_array_equal(host_bits(out), O.generate(ps, st, 9999, O.U32))
+    with pytest.raises(M.MTGPError):
+        g.generate(7, M.KIND_NORMAL_FLOAT32)          # odd count
+    g.close()
+
+
+def test_normals_batch_and_split_plan(M):
+    import torch
+    params = I.draw_param_sets([11213] * 3 + [23209, 44497], 93)
+    seeds = I.state_seeds(len(params))
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    rng = I.SplitMix64(94)
+    b = M.Batch(params, seeds)
+    # eager batch: normals beside the other kinds, even ragged lengths
+    reqs = [(g, [3, 0, 3, 1, 3][g], 2 * rng.uniform_int(1, 30000)) for g in range(len(params))]
+    bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+    b.generate([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+    torch.cuda.synchronize()
+    for (g, k, n), buf in zip(reqs, bufs):
+        if k == 3:
+            assert np.abs(host_f32(buf) - O.normals(params[g], states[g], n)).max() <= NORMAL_ATOL
+        else:
+            np.testing.assert_array_equal(host_bits(buf), O.generate(params[g], states[g], n, k))
+    # a split plan of normals: segments hold whole pairs
+    b.set_split(8)
+    reqs = [(g, 3, 2 * rng.uniform_int(20000, 40000)) for g in range(len(params))]
+    bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+    plan = b.plan([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        for (g, k, n), buf in zip(reqs, bufs):
+            err = np.abs(host_f32(buf) - O.normals(params[g], states[g], n)).max()
+            assert err <= NORMAL_ATOL, f"rep={rep} gen={g} err={err}"
+    plan.close()
+    for g in range(len(params)):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g])
+    with pytest.raises(M.MTGPError):
+        b.generate([(0, 3, 5, bufs[0])])                # odd count
     b.close()

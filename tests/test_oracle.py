@@ -392,3 +392,52 @@ def test_inputs_recipe():
         P.matrix_from_table(p.temper_tbl)
     ps, n1 = I.single_stream()
     assert n1 == 1 << 20 and 2 <= ps[0].pos <= 349
+
+
+# ---------------------------------------------------------------------------
+# Box-Muller normals from float [1,2) pairs (section 6 names the use)
+# ---------------------------------------------------------------------------
+
+def _f32_bits(values):
+    return np.asarray(values, dtype=np.float32).view(np.uint32)
+
+
+def test_normals_invert_to_their_uniforms():
+    """The inverse transform recovers the pair: exp(-(z0^2 + z1^2) / 2) = 2 - a
+    and atan2(z1, z0) / 2 pi = b - 1 (mod 1)."""
+    ps = I.single_stream()[0][0]
+    st = O.seed_state(77, ps.mexp)
+    f12 = O.generate(ps, st.copy(), 20000, O.F12)
+    z = O.normals(ps, st.copy(), 20000)
+    f = f12.view(np.float32).astype(np.float64)
+    a, b = f[0::2], f[1::2]
+    z0, z1 = z[0::2], z[1::2]
+    np.testing.assert_allclose(np.exp(-(z0 * z0 + z1 * z1) / 2.0), 2.0 - a, rtol=1e-12)
+    frac = np.mod(np.arctan2(z1, z0) / (2.0 * np.pi), 1.0)
+    d = np.abs(frac - (b - 1.0))
+    assert np.all(np.minimum(d, 1.0 - d) < 1e-12)
+
+
+def test_normals_special_values():
+    a_max = np.nextafter(np.float32(2.0), np.float32(1.0))        # 2 - 2^-23: u1 = 2^-23
+    r_max = np.sqrt(-2.0 * np.log(2.0 ** -23))
+    z = O.normals_from_f12(_f32_bits([1.0, 1.7, a_max, 1.0, a_max, 1.25, a_max, 1.5]))
+    np.testing.assert_array_equal(z[:2], [0.0, 0.0])               # u1 = 1: radius 0
+    np.testing.assert_allclose(z[2:4], [r_max, 0.0], atol=1e-12)   # angle 0
+    np.testing.assert_allclose(z[4:6], [0.0, r_max], atol=1e-12)   # angle pi/2
+    np.testing.assert_allclose(z[6:8], [-r_max, 0.0], atol=1e-12)  # angle pi
+
+
+def test_normals_are_standard_normal_and_consume_n_steps():
+    from scipy import stats
+    params = I.draw_param_sets([11213] * 4, 91)
+    zs = []
+    for g, ps in enumerate(params):
+        st = O.seed_state(500 + g, ps.mexp)
+        ref = st.copy()
+        zs.append(O.normals(ps, st, 50000))
+        O.advance(ps, ref, 50000)
+        np.testing.assert_array_equal(st, ref)
+    z = np.concatenate(zs)
+    assert abs(z.mean()) < 0.01 and abs(z.var() - 1.0) < 0.01
+    assert stats.kstest(z, stats.norm.cdf).pvalue > 1e-3
