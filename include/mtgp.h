@@ -44,6 +44,7 @@ extern "C" {
 #define MTGP_EINVAL   (-1)   /* bad parameter set, bad argument or alignment */
 #define MTGP_ENOMEM   (-2)   /* host or device allocation failed */
 #define MTGP_EDEVICE  (-3)   /* HIP runtime error; stream position unchanged */
+#define MTGP_ENOTFOUND (-4)  /* parameter search: no set within max_draws */
 
 /* Output kinds (section 6). */
 #define MTGP_KIND_UINT32        0   /* tempered 32-bit word o_{N+k} */
@@ -252,6 +253,36 @@ int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words);
 /* Code of the last failing call on this thread, and a message for a code. */
 int mtgp_last_error(void);
 const char *mtgp_strerror(int code);
+
+/* ---------------------------------------------------------------------------
+ * Parameter search (section 5, MTGPDC's recursion-parameter search), on the
+ * host; no device is used. Draws candidates (M, R) with sh1 = 13, sh2 = 4
+ * (fixed as in section 5), M in 2 < M < N - floor2(N) (2 <= M <= N-1 when that
+ * range is empty), the 32-bit `id` embedded in R -- its 16 MSBs in the 16
+ * MSBs of the first row, its 16 LSBs in bits 19..4 of the second row (the
+ * paper's "12th .. 28th MSB" names 17 positions for 16 bits; the 16 just
+ * above the four LSBs are taken) -- the four LSBs of the rows drawn until
+ * I + R44 is invertible, the remaining bits random. A candidate is accepted
+ * when the minimal polynomial (Berlekamp-Massey) of bit 31 of its raw words
+ * has degree mexp and is irreducible (no factor of degree <= 12, and
+ * x^(2^mexp) = x modulo it): for a Mersenne exponent mexp that means period
+ * 2^mexp - 1. The tempering table is a random F2-linear table (its
+ * equidistribution search needs SIS and is not done). Candidate i uses a
+ * random stream derived from (seed, id, i); the lowest accepted index wins,
+ * so the result does not depend on `threads` (0 = all host cores).
+ * Arguments: mexp prime in 67..65536 (a Mersenne exponent for the period
+ * claim), max_draws > 0, out non-NULL; stats may be NULL. Returns MTGP_OK,
+ * MTGP_EINVAL, or MTGP_ENOTFOUND when max_draws candidates fail.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint64_t draws;          /* index of the accepted candidate + 1 (max_draws if none) */
+    uint64_t evaluated;      /* candidates evaluated by all threads */
+    uint64_t full_degree;    /* of those, linear complexity mexp */
+    uint64_t sieve_passed;   /* of those, no factor of degree <= 12 */
+    double seconds;          /* wall time */
+} mtgp_search_stats;
+int mtgp_search_params(uint32_t mexp, uint32_t id, uint64_t seed, uint64_t max_draws, uint32_t threads,
+                       mtgp_param_set *out, mtgp_search_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -751,6 +751,7 @@ const char *mtgp_strerror(int code)
     case MTGP_EINVAL: return "invalid argument or parameter set";
     case MTGP_ENOMEM: return "out of memory";
     case MTGP_EDEVICE: return "HIP device error";
+    case MTGP_ENOTFOUND: return "no parameter set found within the draw limit";
     default: return "unknown error";
     }
 }

@@ -259,5 +259,129 @@ Poly minpoly(const uint64_t *bits, int64_t n)
     return phi;
 }
 
+// ---------------------------------------------------------------------------
+// Squaring modulo m, and the irreducibility test for prime degree.
+// ---------------------------------------------------------------------------
+
+// 16-bit spread of a byte: bit k moves to bit 2k (squaring over F2 only
+// spreads the coefficients).
+static const uint16_t *spread_table()
+{
+    static uint16_t t[256];
+    static bool init = false;
+    if (!init) {
+        for (int v = 0; v < 256; v++) {
+            uint16_t s = 0;
+            for (int k = 0; k < 8; k++)
+                s |= (uint16_t)(((v >> k) & 1) << (2 * k));
+            t[v] = s;
+        }
+        init = true;
+    }
+    return t;
+}
+
+SquareMod::SquareMod(const Poly &m) : D_(m.deg)
+{
+    spread_table();
+    nw_ = (size_t)((D_ + 63) / 64);
+    tw_ = (size_t)((D_ + 8 + 56) / 64 + 1);
+    // q(c): the byte q with bits D .. D+7 of q m equal to c
+    std::vector<uint8_t> q_of(256, 0);
+    for (int q = 0; q < 256; q++) {
+        int top = 0;
+        for (int b = 0; b < 8; b++)
+            if ((q >> b) & 1)
+                for (int k = 0; k < 8; k++)
+                    if (m.bit(D_ + k - b))
+                        top ^= 1 << k;
+        q_of[(size_t)top] = (uint8_t)q;
+    }
+    table_.assign(8 * 256 * tw_, 0);
+    for (int a = 0; a < 8; a++)
+        for (int c = 0; c < 256; c++) {
+            uint64_t *dst = table_.data() + ((size_t)a * 256 + (size_t)c) * tw_;
+            const int q = q_of[(size_t)c];
+            for (int b = 0; b < 8; b++)
+                if ((q >> b) & 1)
+                    xor_shl(dst, m.w.data(), m.w.size(), 8 * a + b);
+        }
+    work_.assign(2 * nw_ + 2 + tw_, 0);
+}
+
+void SquareMod::square(const uint64_t *a, uint64_t *r)
+{
+    const uint16_t *sp = spread_table();
+    uint64_t *t = work_.data();
+    std::fill(work_.begin(), work_.end(), 0);
+    for (size_t i = 0; i < nw_; i++) {
+        const uint64_t v = a[i];
+        uint64_t lo = 0, hi = 0;
+        for (int k = 0; k < 4; k++) {
+            lo |= (uint64_t)sp[(v >> (8 * k)) & 0xff] << (16 * k);
+            hi |= (uint64_t)sp[(v >> (32 + 8 * k)) & 0xff] << (16 * k);
+        }
+        t[2 * i] = lo;
+        t[2 * i + 1] = hi;
+    }
+    // clear the bytes above x^D, top down: byte j covers x^(D+8j) .. x^(D+8j+7)
+    for (int64_t j = (D_ - 2) / 8; j >= 0; j--) {
+        const int64_t e = D_ + 8 * j;
+        const size_t wi = (size_t)(e >> 6);
+        const int sh = (int)(e & 63);
+        uint64_t c = t[wi] >> sh;
+        if (sh > 56)
+            c |= t[wi + 1] << (64 - sh);
+        c &= 0xff;
+        if (!c)
+            continue;
+        // q(c) m shifted by 8j: word offset 8j / 64, alignment (8j mod 64) / 8
+        const int64_t s = 8 * j;
+        const uint64_t *src = table_.data() + ((size_t)((s & 63) >> 3) * 256 + (size_t)c) * tw_;
+        uint64_t *dst = t + (size_t)(s >> 6);
+        for (size_t k = 0; k < tw_; k++)
+            dst[k] ^= src[k];
+    }
+    std::copy(t, t + nw_, r);
+}
+
+bool irreducible_prime_degree(const Poly &m, uint32_t sieve, bool *sieved)
+{
+    if (sieved)
+        *sieved = false;
+    const int64_t p = m.deg;
+    if (p < 8 || !m.bit(0))
+        return false;   // x divides m (or too small for the byte tables)
+    int terms = 0;
+    for (uint64_t w : m.w)
+        terms += __builtin_popcountll(w);
+    if ((terms & 1) == 0)
+        return false;   // m(1) = 0: x + 1 divides m
+    SquareMod sm(m);
+    const size_t nw = sm.words();
+    std::vector<uint64_t> r(nw, 0), t(nw, 0);
+    r[0] = 2;   // x
+    for (int64_t k = 1; k <= p; k++) {
+        sm.square(r.data(), t.data());
+        r.swap(t);
+        if ((uint32_t)k <= sieve) {
+            // gcd(m, x^(2^k) - x) = 1, else m has a factor of degree dividing k
+            Poly g;
+            g.w = r;
+            g.w[0] ^= 2;
+            g.trim();
+            if (g.deg >= 0 && gcd(m, g).deg > 0)
+                return false;
+            if ((uint32_t)k == sieve && sieved)
+                *sieved = true;
+        }
+    }
+    r[0] ^= 2;
+    for (uint64_t w : r)
+        if (w)
+            return false;
+    return true;
+}
+
 }  // namespace f2
 }  // namespace mtgp_impl

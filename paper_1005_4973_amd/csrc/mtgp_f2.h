@@ -36,5 +36,28 @@ Poly powmod_x(uint64_t e, const Poly &m);     // x^e mod m
 // of the bit sequence s_0 .. s_{n-1}, packed like a polynomial.
 Poly minpoly(const uint64_t *bits, int64_t n);
 
+// Squaring modulo a fixed polynomial m of degree D >= 8, reduced eight
+// coefficients at a time: for every value c of the byte above x^D, the
+// multiple q(c) m whose coefficients of x^D .. x^{D+7} spell c is stored
+// pre-shifted for the eight byte positions within a 64-bit word, so one
+// reduction step is one word-aligned XOR of about D/64 words.
+class SquareMod {
+public:
+    explicit SquareMod(const Poly &m);
+    size_t words() const { return nw_; }           // words of a reduced polynomial
+    void square(const uint64_t *a, uint64_t *r);   // r = a^2 mod m (a reduced, words() long)
+
+private:
+    int64_t D_;
+    size_t nw_, tw_;                 // reduced words, table entry words
+    std::vector<uint64_t> table_;    // [8 alignments][256 bytes][tw_ words]
+    std::vector<uint64_t> work_;     // 2 nw_ + 2 words
+};
+
+// Irreducibility of m when its degree p is prime: m(0) = m(1) = 1, no factor
+// of degree <= sieve (gcd(m, x^(2^k) - x) = 1 for k <= sieve), and
+// x^(2^p) = x mod m. *sieved is set when the sieve passed.
+bool irreducible_prime_degree(const Poly &m, uint32_t sieve, bool *sieved);
+
 }  // namespace f2
 }  // namespace mtgp_impl

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Iterable, List, Optional, Sequence
+from typing import Iterable, List, NamedTuple, Optional, Sequence
 
 import torch  # loads torch's HIP runtime first, so the library shares it
 
@@ -40,6 +40,11 @@ class ParamSetC(ctypes.Structure):
     _fields_ = [("mexp", ctypes.c_uint32), ("pos", ctypes.c_uint32),
                 ("sh1", ctypes.c_uint32), ("sh2", ctypes.c_uint32),
                 ("param_tbl", ctypes.c_uint32 * 16), ("temper_tbl", ctypes.c_uint32 * 16)]
+
+
+class SearchStatsC(ctypes.Structure):
+    _fields_ = [("draws", ctypes.c_uint64), ("evaluated", ctypes.c_uint64), ("full_degree", ctypes.c_uint64),
+                ("sieve_passed", ctypes.c_uint64), ("seconds", ctypes.c_double)]
 
 
 class TuningC(ctypes.Structure):
@@ -84,6 +89,8 @@ _SIGNATURES = {
     "mtgp_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mtgp_plan_launch_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "mtgp_batch_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_search_params": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint32, ctypes.POINTER(ParamSetC), ctypes.POINTER(SearchStatsC)]),
     "mtgp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_uint32, ctypes.POINTER(TuningC)]),
     "mtgp_plan_destroy": (None, [ctypes.c_void_p]),
@@ -120,6 +127,29 @@ def strerror(code: int) -> str:
 
 def state_words(mexp: int) -> int:
     return int(lib().mtgp_state_words(mexp))
+
+
+class FoundParams(NamedTuple):
+    """A parameter set from search_params (same fields as the parameter sets
+    the other calls take)."""
+    mexp: int
+    pos: int
+    sh1: int
+    sh2: int
+    param_tbl: tuple
+    temper_tbl: tuple
+
+
+def search_params(mexp: int, id: int = 0, seed: int = 1, max_draws: int = 1 << 20, threads: int = 0):
+    """Recursion-parameter search of period 2^mexp - 1 with `id` embedded
+    (mtgp_search_params; host only). Returns (FoundParams, stats dict)."""
+    p = ParamSetC()
+    st = SearchStatsC()
+    rc = lib().mtgp_search_params(mexp, id & 0xFFFFFFFF, seed, max_draws, threads, ctypes.byref(p), ctypes.byref(st))
+    _check(rc, "mtgp_search_params")
+    stats = {"draws": st.draws, "evaluated": st.evaluated, "full_degree": st.full_degree,
+             "sieve_passed": st.sieve_passed, "seconds": round(st.seconds, 3)}
+    return FoundParams(p.mexp, p.pos, p.sh1, p.sh2, tuple(p.param_tbl), tuple(p.temper_tbl)), stats
 
 
 def _param_c(ps) -> ParamSetC:
