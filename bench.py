@@ -17,6 +17,8 @@ The same JSON line also reports:
                   lengths log-uniform in [2^10, 2^24], mixed kinds: one
                   graph-captured persistent launch vs one launch per request
   large_states    256 generators at p = 23209 and at p = 44497, 2^24 uint32 each
+  normals         the headline generators, 2^22 Box-Muller normals each (float32)
+  param_search    host-side search for full-period parameter sets (p = 4423, 11213)
   single_stream   one MTGP-11213 generator, 2^20 uint32 (one eager call)
   serving         65536 resident MTGP-11213 states, Poisson arrivals at a swept
                   fraction of the measured saturation rate, log-normal sizes
@@ -36,7 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("batched_uneven", "large_states", "single_stream", "serving")
+SECTIONS = ("batched_uneven", "large_states", "normals", "single_stream", "serving", "param_search")
 
 
 def parse():
@@ -258,6 +260,38 @@ def large_states(torch, I, mtgp):
     return res
 
 
+def normals(torch, I, mtgp):
+    """128 MTGP-11213 generators x 2^22 Gaussian deviates (Box-Muller on pairs of
+    float [1,2) outputs), one tuned split plan replayed."""
+    params, n = I.independent_128()
+    G = len(params)
+    batch = mtgp.Batch(params, I.state_seeds(G))
+    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+    rq = [(g, mtgp.KIND_NORMAL_FLOAT32, n, out.data_ptr() + 4 * g * n) for g in range(G)]
+    tuning = batch.autotune(rq, reps=2)
+    plan = batch.plan(rq)
+    ms = timed_ms(torch, lambda: plan.launch(), reps=5)
+    plan.close()
+    batch.close()
+    del out
+    torch.cuda.empty_cache()
+    alg = G * (4 * n + 8 * 351 + 256)
+    return {"generators": G, "numbers": G * n, "ms": round(ms, 3), "G_normals_s": round(G * n / ms / 1e6, 2),
+            **roof(alg, ms / 1e3), "autotuned": tuning}
+
+
+def param_search(torch, I, mtgp):
+    """Host-side recursion-parameter search (section 5): full-period sets with
+    an ID embedded, seeded so the draw counts are fixed; the paper's own
+    search took 338 s per MTGP-11213 set on average (context only)."""
+    threads = min(16, len(os.sched_getaffinity(0)))
+    runs = []
+    for mexp, ident in ((4423, 1), (11213, 1), (11213, 4)):
+        _, st = mtgp.search_params(mexp, id=ident, seed=mexp, threads=threads)
+        runs.append({"mexp": mexp, "id": ident, "draws": st["draws"], "seconds": st["seconds"]})
+    return {"threads": threads, "runs": runs}
+
+
 def single_stream(torch, I, mtgp):
     (ps,), n = I.single_stream()
     g = mtgp.Generator(ps, 1234)
@@ -341,8 +375,8 @@ def main():
         res["cpu_baseline"] = cpu_baseline(params, n, kinds, threads)
         log(f"cpu baseline: {res['cpu_baseline']['value']} G numbers/s")
     sections = [s for s in args.sections.split(",") if s]
-    fns = {"batched_uneven": batched_uneven, "large_states": large_states, "single_stream": single_stream,
-           "serving": serving}
+    fns = {"batched_uneven": batched_uneven, "large_states": large_states, "normals": normals,
+           "single_stream": single_stream, "serving": serving, "param_search": param_search}
     for name in sections:
         t0 = time.perf_counter()
         res[name] = fns[name](torch, I, mtgp)

@@ -16,6 +16,8 @@
 #include "../../include/mtgp.h"
 #include "mtgp_f2.h"
 
+#include <sched.h>
+
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -41,7 +43,7 @@ struct SplitMix64 {
 };
 
 constexpr uint32_t kSh1 = 13, kSh2 = 4;
-constexpr uint32_t kSieve = 12;   // reject factors of degree <= 12 before the full test
+constexpr uint32_t kSieve = 28;   // reject factors of degree <= 28 before the full test
 
 struct Candidate {
     uint32_t M;
@@ -172,8 +174,13 @@ extern "C" int mtgp_search_params(uint32_t mexp, uint32_t id, uint64_t seed, uin
     if (!out || !is_prime(mexp) || mexp < 67 || mexp > 65536 || max_draws == 0)
         return MTGP_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
-    if (threads == 0)
-        threads = std::max(1u, std::thread::hardware_concurrency());
+    if (threads == 0) {
+        // the CPUs this process may run on, at most 16
+        cpu_set_t set;
+        CPU_ZERO(&set);
+        const int n = sched_getaffinity(0, sizeof(set), &set) == 0 ? CPU_COUNT(&set) : 1;
+        threads = (uint32_t)std::min(16, std::max(1, n));
+    }
     std::atomic<uint64_t> next{0};
     std::atomic<uint64_t> best{UINT64_MAX};
     std::atomic<uint64_t> n_full{0}, n_sieved{0}, n_tested{0};
