@@ -19,7 +19,8 @@ The same JSON line also reports:
   large_states    256 generators at p = 23209 and at p = 44497, 2^24 uint32 each
   normals         the headline generators, 2^22 Box-Muller normals each (float32)
   param_search    host-side search for full-period parameter sets (p = 4423, 11213)
-  single_stream   one MTGP-11213 generator, 2^20 uint32 (one eager call)
+  single_stream   one MTGP-11213 generator, 2^20 uint32 per eager call, unsplit
+                  and split into jump-ahead segments
   serving         65536 resident MTGP-11213 states, Poisson arrivals at a swept
                   fraction of the measured saturation rate, log-normal sizes
                   (median 2^16, sigma 1.5, clipped to [2^10, 2^26]):
@@ -293,12 +294,24 @@ def param_search(torch, I, mtgp):
 
 
 def single_stream(torch, I, mtgp):
+    """One generator, 2^20 uint32 per eager call: as one workgroup (the
+    recursion's rounds in sequence), and split into jump-ahead segments (the
+    first split call finds the orbit's annihilator and the jump polynomials;
+    the timed calls reuse them)."""
     (ps,), n = I.single_stream()
     g = mtgp.Generator(ps, 1234)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     ms = timed_ms(torch, lambda: g.generate(n, I.KIND_U32, out=out), reps=5)
+    g.set_split(16)
+    t0 = time.perf_counter()
+    g.generate(n, I.KIND_U32, out=out)
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    ms_split = timed_ms(torch, lambda: g.generate(n, I.KIND_U32, out=out), reps=5)
     g.close()
-    return {"M": ps.pos, "numbers": n, "ms": round(ms, 4), "G_numbers_s": round(n / ms / 1e6, 3)}
+    return {"M": ps.pos, "numbers": n, "ms": round(ms, 4), "G_numbers_s": round(n / ms / 1e6, 3),
+            "split_16_rounds": {"ms": round(ms_split, 4), "G_numbers_s": round(n / ms_split / 1e6, 3),
+                                "first_call_s": round(first_s, 3)}}
 
 
 def serving(torch, I, mtgp):

@@ -109,6 +109,21 @@ int mtgp_generate_float32_1to2(mtgp_t *g, size_t n, float *out, void *stream);
 int mtgp_generate_float32_0to1(mtgp_t *g, size_t n, float *out, void *stream);
 int mtgp_generate_normal_float32(mtgp_t *g, size_t n, float *out, void *stream);   /* n even */
 
+/*
+ * Jump-ahead for this generator's calls (section 7 discusses jumping ahead):
+ * with max_rounds > 0, a call that needs more than max_rounds rounds runs as
+ * S segments that generate concurrently -- segment k starts from F^{kJ} S,
+ * computed on the device from the current state's raw words and
+ * h_k = x^{kJ} mod psi (psi annihilates the state's orbit, found on the host
+ * with Berlekamp-Massey on the first split call, and again after
+ * mtgp_set_state). The jump polynomials and device buffers are kept for the
+ * last segment length, so repeated calls of one length pay only the
+ * kernels. Outputs are identical to the unsplit stream. The first split call
+ * synchronises `stream` once (to read the raw words back). 0 (default)
+ * disables.
+ */
+int mtgp_set_split(mtgp_t *g, uint32_t max_rounds);
+
 /* Release the handle (NULL-safe); waits for work queued on its last stream. */
 void mtgp_destroy(mtgp_t *g);
 

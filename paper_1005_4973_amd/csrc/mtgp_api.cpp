@@ -196,6 +196,21 @@ struct mtgp {
     hipStream_t last = nullptr;
     LaunchShape shape;
     size_t max_lds = 65536;
+    int cu_count = 0;
+    // jump-ahead for long calls
+    uint32_t split_rounds = 0;                 // 0: never split a call
+    f2::Poly psi;                              // annihilator of the orbit (deg < 1: not known)
+    bool psi_known = false;
+    uint64_t split_J = 0;                      // segment length the buffers below were made for
+    uint32_t split_S = 0;
+    char *d_split = nullptr;                   // [raw][polynomials][segment states][jump items][work items][counters]
+    uint32_t *d_raw = nullptr, *d_seg = nullptr, *d_counters = nullptr;
+    JumpItem *d_jumps = nullptr;
+    WorkItem *d_items = nullptr;
+    std::vector<JumpItem> jumps;               // host copy, for the launch grouping
+    WorkItem *h_items = nullptr;               // pinned staging of the segment items
+    hipEvent_t items_free = nullptr;           // the staging copy of the previous split call is done
+    bool items_pending = false;
 };
 
 struct mtgp_batch {
@@ -589,6 +604,49 @@ int ensure_annihilators(mtgp_batch *b, const std::vector<uint32_t> &gens)
     return MTGP_OK;
 }
 
+// Segments for a request of n outputs needing `rounds` rounds: S segments of
+// J outputs (the last takes the rest), J even so normals keep their pairs.
+// At most kMaxSegments per request: more would not run at once, and each
+// costs a jump and a host polynomial product.
+constexpr uint64_t kMaxSegments = 1024;
+
+void split_count(uint64_t n, uint64_t rounds, uint32_t split_rounds, uint32_t &S, uint64_t &J)
+{
+    S = (uint32_t)std::min<uint64_t>((rounds + split_rounds - 1) / split_rounds, kMaxSegments);
+    auto seg_len = [&](uint32_t s) { return ((n + s - 1) / s + 1) & ~(uint64_t)1; };
+    J = seg_len(S);
+    while (S > 1 && (uint64_t)(S - 1) * J >= n) {
+        S--;
+        J = seg_len(S);
+    }
+}
+
+// Jump polynomials h_k = x^{kJ} mod psi, k = 1 .. S-1.
+std::vector<f2::Poly> jump_polys(const f2::Poly &psi, uint64_t J, uint32_t S)
+{
+    std::vector<f2::Poly> h;
+    if (S < 2)
+        return h;
+    const f2::Poly g = f2::powmod_x(J, psi);
+    h.push_back(g);
+    for (uint32_t k = 2; k < S; k++)
+        h.push_back(f2::mulmod(h.back(), g, psi));
+    return h;
+}
+
+// h in the jump kernel's layout (JumpItem): bit e of h is bit e % R of block
+// e / R, four 16-bit blocks per word; dst has jump_poly_words(N, deg psi)
+// zeroed words.
+void layout_poly(const f2::Poly &h, uint32_t N, uint64_t *dst)
+{
+    const uint32_t R = jump_shape(N).R;
+    for (int64_t e = 0; e <= h.deg; e++)
+        if (h.bit(e)) {
+            const uint64_t blk = (uint64_t)e / R;
+            dst[blk / 4] |= 1ull << (16 * (blk % 4) + (uint64_t)e % R);
+        }
+}
+
 struct SplitSpec {
     size_t item;        // index in the request's item list
     uint32_t gen;
@@ -609,14 +667,9 @@ int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem>
         const uint64_t rounds = (items[i].n + w - 1) / w;
         if (rounds <= b->split_rounds)
             continue;
-        // J is even, so normals keep their pairs inside a segment
-        uint32_t S = (uint32_t)((rounds + b->split_rounds - 1) / b->split_rounds);
-        auto seg_len = [&](uint32_t s) { return ((items[i].n + s - 1) / s + 1) & ~(uint64_t)1; };
-        uint64_t J = seg_len(S);
-        while (S > 1 && (uint64_t)(S - 1) * J >= items[i].n) {
-            S--;
-            J = seg_len(S);
-        }
+        uint32_t S;
+        uint64_t J;
+        split_count(items[i].n, rounds, b->split_rounds, S, J);
         if (S > 1)
             specs.push_back({i, items[i].gen, S, J});
     }
@@ -636,13 +689,7 @@ int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem>
         return MTGP_OK;
     // jump polynomials h_k = x^{kJ} mod psi, k = 1 .. S-1
     std::vector<std::vector<f2::Poly>> polys(ok.size());
-    parallel_for(ok.size(), [&](size_t i) {
-        const f2::Poly &psi = b->psi[ok[i].gen];
-        const f2::Poly g = f2::powmod_x(ok[i].J, psi);
-        polys[i].push_back(g);
-        for (uint32_t k = 2; k < ok[i].S; k++)
-            polys[i].push_back(f2::mulmod(polys[i].back(), g, psi));
-    });
+    parallel_for(ok.size(), [&](size_t i) { polys[i] = jump_polys(b->psi[ok[i].gen], ok[i].J, ok[i].S); });
     // device layout: [raw words][polynomials][segment states]
     std::vector<size_t> raw_off(ok.size()), poly_off(ok.size()), seg_off(ok.size());
     size_t bytes = 0;
@@ -671,7 +718,6 @@ int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem>
         const uint32_t N = r.N;
         const uint32_t D = (uint32_t)b->psi[sp.gen].deg;
         const uint32_t pw = jump_poly_words(N, D);
-        const uint32_t R = jump_shape(N).R;
         uint32_t *raw = reinterpret_cast<uint32_t *>(mem + raw_off[i]);
         uint32_t *seg = reinterpret_cast<uint32_t *>(mem + seg_off[i]);
         // prefix: the state and D - 1 new raw words (states stay put)
@@ -683,14 +729,7 @@ int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem>
         pre.kind = kKindRaw | kKeepState;
         prefix.push_back(pre);
         for (uint32_t k = 1; k < sp.S; k++) {
-            const f2::Poly &h = polys[i][k - 1];
-            // bit e of h is bit e % R of block e / R (see JumpItem)
-            uint64_t *dst = hpoly.data() + (poly_off[i] / 8) + (size_t)(k - 1) * pw;
-            for (int64_t e = 0; e <= h.deg; e++)
-                if (h.bit(e)) {
-                    const uint64_t blk = (uint64_t)e / R;
-                    dst[blk / 4] |= 1ull << (16 * (blk % 4) + (uint64_t)e % R);
-                }
+            layout_poly(polys[i][k - 1], N, hpoly.data() + (poly_off[i] / 8) + (size_t)(k - 1) * pw);
             JumpItem j;
             std::memset(&j, 0, sizeof(j));
             j.raw = reinterpret_cast<uint64_t>(raw);
@@ -790,7 +829,167 @@ mtgp_t *mtgp_create(const mtgp_param_set *ps, uint32_t seed)
     }
     g->max_lds = device_max_lds();
     g->shape = single_shape(g->rec, g->max_lds);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        g->cu_count = prop.multiProcessorCount;
     return g;
+}
+
+// A long call as S segments (section 7): the raw prefix of the current
+// state, the S-1 jump correlations, then one persistent launch over the
+// segments, all on `s`. The orbit's annihilator is found on the first split
+// call (and after set_state); the jump polynomials and device buffers are
+// kept for the last segment length used. Returns MTGP_ENOTFOUND when no
+// annihilator exists (the caller runs the call unsplit).
+static int generate_split(mtgp_t *g, uint64_t n, void *out, hipStream_t s, uint32_t kind)
+{
+    const GenRecord &r = g->rec;
+    const uint32_t N = r.N;
+    WorkItem none;
+    std::memset(&none, 0, sizeof(none));
+    if (!g->psi_known) {
+        // raw words of the current state: the N state words and 2p + 65 more
+        const uint64_t steps = raw_steps_for(g->ps.mexp);
+        std::vector<uint32_t> raw(N + steps);
+        uint32_t *d_raw = nullptr;
+        if (hipMalloc(&d_raw, raw.size() * sizeof(uint32_t)) != hipSuccess)
+            return MTGP_ENOMEM;
+        WorkItem it = none;
+        it.out = reinterpret_cast<uint64_t>(d_raw);
+        it.n = steps;
+        it.kind = kKindRaw | kKeepState;
+        it.spl = item_spl(N, r.M, g->shape);
+        const bool ok = launch_generate(g->d_rec, g->d_state, nullptr, 1, nullptr, it, g->shape, s) == hipSuccess &&
+                        hipMemcpyAsync(raw.data(), d_raw, raw.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s) ==
+                            hipSuccess &&
+                        hipStreamSynchronize(s) == hipSuccess;
+        hipFree(d_raw);
+        if (!ok)
+            return MTGP_EDEVICE;
+        g->psi = orbit_annihilator(raw.data(), raw.size(), N, g->ps.mexp);
+        g->psi_known = true;
+    }
+    if (g->psi.deg < 1)
+        return MTGP_ENOTFOUND;
+    const uint32_t D = (uint32_t)g->psi.deg;
+    const uint64_t w = round_width(N, r.M, g->shape);
+    uint32_t S;
+    uint64_t J;
+    split_count(n, (n + w - 1) / w, g->split_rounds, S, J);
+    if (S < 2)
+        return MTGP_ENOTFOUND;
+    if (J != g->split_J || S != g->split_S) {
+        // buffers and jump polynomials for this segment length
+        if (hipStreamSynchronize(g->last) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return MTGP_EDEVICE;
+        hipFree(g->d_split);
+        g->d_split = nullptr;
+        g->split_J = 0;
+        g->split_S = 0;
+        const uint32_t pw = jump_poly_words(N, D);
+        size_t off = 0;
+        const size_t raw_off = off;
+        off = align256(off + (size_t)(N + D) * 4u);
+        const size_t poly_off = off;
+        off = align256(off + (size_t)(S - 1) * pw * 8u);
+        const size_t seg_off = off;
+        off = align256(off + (size_t)(S - 1) * N * 4u);
+        const size_t jump_off = off;
+        off = align256(off + (size_t)(S - 1) * sizeof(JumpItem));
+        const size_t item_off = off;
+        off = align256(off + (size_t)S * sizeof(WorkItem));
+        const size_t ctr_off = off;
+        off += 2 * sizeof(uint32_t);
+        char *mem = nullptr;
+        if (hipMalloc(&mem, off) != hipSuccess)
+            return MTGP_ENOMEM;
+        g->d_split = mem;
+        g->d_raw = reinterpret_cast<uint32_t *>(mem + raw_off);
+        g->d_seg = reinterpret_cast<uint32_t *>(mem + seg_off);
+        g->d_jumps = reinterpret_cast<JumpItem *>(mem + jump_off);
+        g->d_items = reinterpret_cast<WorkItem *>(mem + item_off);
+        g->d_counters = reinterpret_cast<uint32_t *>(mem + ctr_off);
+        const std::vector<f2::Poly> h = jump_polys(g->psi, J, S);
+        std::vector<uint64_t> hpoly((size_t)(S - 1) * pw, 0);
+        g->jumps.assign(S - 1, JumpItem{});
+        for (uint32_t k = 1; k < S; k++) {
+            layout_poly(h[k - 1], N, hpoly.data() + (size_t)(k - 1) * pw);
+            JumpItem &j = g->jumps[k - 1];
+            std::memset(&j, 0, sizeof(j));
+            j.raw = reinterpret_cast<uint64_t>(g->d_raw);
+            j.poly = reinterpret_cast<uint64_t>(mem + poly_off + (size_t)(k - 1) * pw * 8u);
+            j.out = reinterpret_cast<uint64_t>(g->d_seg + (size_t)(k - 1) * N);
+            j.D = D;
+            j.N = N;
+        }
+        if (hipMemcpy(mem + poly_off, hpoly.data(), hpoly.size() * 8u, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g->d_jumps, g->jumps.data(), g->jumps.size() * sizeof(JumpItem), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemset(g->d_counters, 0, 2 * sizeof(uint32_t)) != hipSuccess)
+            return MTGP_EDEVICE;
+        if (g->h_items)
+            hipHostFree(g->h_items);
+        g->h_items = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void **>(&g->h_items), (size_t)S * sizeof(WorkItem)) != hipSuccess)
+            return MTGP_ENOMEM;
+        if (!g->items_free && hipEventCreateWithFlags(&g->items_free, hipEventDisableTiming) != hipSuccess)
+            return MTGP_EDEVICE;
+        g->items_pending = false;
+        g->split_J = J;
+        g->split_S = S;
+    }
+    // segment items: segment k writes outputs [kJ, kJ + J) from its start state
+    if (g->items_pending && hipEventSynchronize(g->items_free) != hipSuccess)
+        return MTGP_EDEVICE;
+    LaunchShape sh;
+    {
+        std::vector<WorkItem> items(S);
+        for (uint32_t k = 0; k < S; k++) {
+            WorkItem &it = items[k];
+            std::memset(&it, 0, sizeof(it));
+            it.out = reinterpret_cast<uint64_t>(out) + 4u * (uint64_t)k * J;
+            it.n = k + 1 < S ? J : n - (uint64_t)k * J;
+            it.kind = (uint16_t)(kind | (k + 1 < S ? kKeepState : 0));
+            it.src = k == 0 ? reinterpret_cast<uint64_t>(g->d_raw)
+                            : reinterpret_cast<uint64_t>(g->d_seg + (size_t)(k - 1) * N);
+        }
+        // the launch shape of the segments: 256-lane workgroups, as many per
+        // CU as the segments need (up to 8), each with an even share of LDS
+        sh.mode = kModeGroup;
+        sh.threads = 256;
+        sh.spl = 4;
+        sh.grid = 1;
+        sh.lds_words = 1;
+        const uint32_t cus = (uint32_t)std::max(1, g->cu_count);
+        const uint32_t kpc = std::max(1u, std::min(8u, (S + cus - 1) / cus));
+        const size_t share = (kLdsPerCu / kpc) / 1024u * 1024u - 1024u;
+        const uint32_t need = window_need(r, sh);
+        const uint32_t cap = max_window_words(sh, g->max_lds);
+        sh.lds_words = (int)std::min(cap, std::max(need, (uint32_t)(share / 4u - kUnitLdsExtra)));
+        sh.grid = (int)std::min<uint64_t>(S, (uint64_t)kpc * cus);
+        if (!shape_valid(sh, g->max_lds) || (uint32_t)sh.lds_words < need)
+            return MTGP_EINVAL;
+        for (WorkItem &it : items)
+            it.spl = item_spl(N, r.M, sh);
+        std::memcpy(g->h_items, items.data(), items.size() * sizeof(WorkItem));
+    }
+    WorkItem pre = none;
+    pre.out = reinterpret_cast<uint64_t>(g->d_raw);
+    pre.n = D - 1;
+    pre.kind = kKindRaw | kKeepState;
+    pre.spl = item_spl(N, r.M, g->shape);
+    if (hipMemcpyAsync(g->d_items, g->h_items, (size_t)S * sizeof(WorkItem), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(g->items_free, s) != hipSuccess)
+        return MTGP_EDEVICE;
+    g->items_pending = true;
+    if (launch_generate(g->d_rec, g->d_state, nullptr, 1, nullptr, pre, g->shape, s) != hipSuccess ||
+        launch_jumps(g->d_jumps, g->jumps.data(), (uint32_t)g->jumps.size(), s) != hipSuccess ||
+        launch_generate(g->d_rec, g->d_state, g->d_items, S, g->d_counters, none, sh, s) != hipSuccess)
+        return MTGP_EDEVICE;
+    g->consumed += n;
+    g->last = s;
+    return MTGP_OK;
 }
 
 static int generate_kind(mtgp_t *g, size_t n, void *out, void *stream, uint32_t kind)
@@ -804,6 +1003,14 @@ static int generate_kind(mtgp_t *g, size_t n, void *out, void *stream, uint32_t 
     if (n == 0)
         return MTGP_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->split_rounds > 0) {
+        const uint64_t w = round_width(g->rec.N, g->rec.M, g->shape);
+        if ((n + w - 1) / w > g->split_rounds) {
+            const int rc = generate_split(g, n, out, s, kind);
+            if (rc != MTGP_ENOTFOUND)   // no annihilator: run the call unsplit
+                return rc == MTGP_OK ? MTGP_OK : fail(rc);
+        }
+    }
     WorkItem it;
     std::memset(&it, 0, sizeof(it));
     it.out = reinterpret_cast<uint64_t>(out);
@@ -845,6 +1052,11 @@ void mtgp_destroy(mtgp_t *g)
     hipStreamSynchronize(g->last);
     hipFree(g->d_rec);
     hipFree(g->d_state);
+    hipFree(g->d_split);
+    if (g->h_items)
+        hipHostFree(g->h_items);
+    if (g->items_free)
+        hipEventDestroy(g->items_free);
     delete g;
 }
 
@@ -868,6 +1080,17 @@ int mtgp_set_state(mtgp_t *g, const uint32_t *host_words, uint64_t consumed)
         hipMemcpy(g->d_state, host_words, g->rec.N * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
         return fail(MTGP_EDEVICE);
     g->consumed = consumed;
+    g->psi_known = false;   // the orbit may have changed: annihilator and jump polynomials are stale
+    g->split_J = 0;
+    g->split_S = 0;
+    return MTGP_OK;
+}
+
+int mtgp_set_split(mtgp_t *g, uint32_t max_rounds)
+{
+    if (!g)
+        return fail(MTGP_EINVAL);
+    g->split_rounds = max_rounds;
     return MTGP_OK;
 }
 

@@ -89,6 +89,7 @@ _SIGNATURES = {
     "mtgp_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mtgp_plan_launch_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "mtgp_batch_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_search_params": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                           ctypes.c_uint32, ctypes.POINTER(ParamSetC), ctypes.POINTER(SearchStatsC)]),
     "mtgp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p,
@@ -213,6 +214,10 @@ class Generator:
 
     def generate_normal_float32(self, n, out=None, stream=None):
         return self.generate(n, KIND_NORMAL_FLOAT32, out, stream)
+
+    def set_split(self, max_rounds: int):
+        """Split calls longer than max_rounds rounds into jump-ahead segments (0: off)."""
+        _check(lib().mtgp_set_split(self._h, max_rounds), "mtgp_set_split")
 
     def set_launch(self, mode: int = -1, threads: int = 0, spl: int = 1, lds_words: int = 0):
         """Override the launch shape (mode -1 restores the automatic choice)."""

@@ -496,3 +496,32 @@ def test_normals_batch_and_split_plan(M):
     with pytest.raises(M.MTGPError):
         b.generate([(0, 3, 5, bufs[0])])                # odd count
     b.close()
+
+
+def test_single_generator_split_calls(M):
+    """Eager calls split into jump-ahead segments equal the unsplit stream,
+    across lengths (the jump buffers are rebuilt), kinds and set_state."""
+    params = I.draw_param_sets([11213], 95) + I.draw_param_sets([23209], 96)
+    d = __import__("json").load(open(os.path.join(os.path.dirname(__file__), "golden", "fullperiod_sets.json")))
+    e = [x for x in d["sets"] if x["mexp"] == 2203][0]
+    params.append(I.ParamSet(e["mexp"], e["pos"], e["sh1"], e["sh2"], tuple(e["param_tbl"]), tuple(e["temper_tbl"])))
+    for ps in params:
+        st = O.seed_state(41, ps.mexp)
+        g = M.Generator(ps, 41)
+        g.set_split(8)
+        for n, kind in ((100000, 0), (100000, 1), (2 * 40001, 3), (999, 0), (250001, 2), (100000, 0)):
+            say(f"split call mexp={ps.mexp} n={n} kind={kind}")
+            out = g.generate(n, kind)
+            if kind == 3:
+                assert np.abs(host_f32(out) - O.normals(ps, st, n)).max() <= NORMAL_ATOL
+            else:
+                np.testing.assert_array_equal(host_bits(out), O.generate(ps, st, n, kind),
+                                              err_msg=f"mexp={ps.mexp} n={n} kind={kind}")
+        words, consumed = g.get_state()
+        np.testing.assert_array_equal(words, st)
+        # a new state: the annihilator and the jump polynomials are rebuilt
+        st2 = O.seed_state(777, ps.mexp)
+        g.set_state(st2, 0)
+        out = g.generate(100000, 0)
+        np.testing.assert_array_equal(host_bits(out), O.generate(ps, st2, 100000, 0))
+        g.close()
