@@ -21,8 +21,9 @@ The same JSON line also reports:
   param_search    host-side search for full-period parameter sets (p = 4423, 11213)
   single_stream   one MTGP-11213 generator, 2^20 uint32 per eager call, unsplit
                   and split into jump-ahead segments
-  serving         65536 resident MTGP-11213 states, Poisson arrivals at a swept
-                  fraction of the measured saturation rate, log-normal sizes
+  serving         65536 resident MTGP-11213 states behind the library's native
+                  request loop, Poisson arrivals at a swept fraction of the
+                  measured saturation rate, log-normal sizes
                   (median 2^16, sigma 1.5, clipped to [2^10, 2^26]):
                   p50/p99 latency and sustained numbers/s
 `value` is numbers/s with states and parameters resident in HBM when the
@@ -315,36 +316,52 @@ def single_stream(torch, I, mtgp):
 
 
 def serving(torch, I, mtgp):
+    """65536 resident MTGP-11213 states served by the library's request loop
+    (mtgp_server_*, native admission and tick building; Python only feeds
+    arrivals): saturation rate with all requests available at once, then
+    Poisson arrivals at fractions of it. One point with the Python loop
+    (serve.Server) is kept for comparison."""
     from paper_1005_4973_amd import serve
     G = 65536
     params = I.serving_params(G)
     batch = mtgp.Batch(params, I.state_seeds(G))
+    arena, chunk = 8 << 30, 1 << 18
 
-    def run(trace, realtime):
-        srv = serve.Server(serve.GpuExecutor(batch), mem_budget_bytes=8 << 30, chunk=1 << 18, depth=2,
-                           keep_outputs=False)
-        return srv.run(trace, realtime=realtime)
+    def native(trace, realtime):
+        srv = serve.NativeServer(batch, arena_bytes=arena, chunk=chunk, depth=2)
+        st = srv.run(trace, realtime=realtime)
+        srv.close()
+        return st
 
-    # saturation: every request available at once
-    sat_trace = I.serving_trace(3000, rate_per_s=1.0, num_gens=G, seed=5001)
-    run(sat_trace[:300], False)          # warm-up
-    st = run(sat_trace, False)
+    def point(load, st, lam=None, num=None):
+        d = {"load": load, "req_per_s": round(lam if lam is not None else st.completed / st.wall_s, 1),
+             "completed": st.completed, "numbers_per_s": round(st.numbers / st.wall_s, 1),
+             "p50_ms": round(st.percentile(50) * 1e3, 3), "p99_ms": round(st.percentile(99) * 1e3, 3)}
+        if num is not None:
+            d["requests"] = num
+        return d
+
+    sat_trace = I.serving_trace(20000, rate_per_s=1.0, num_gens=G, seed=5001)
+    native(sat_trace[:500], False)          # warm-up
+    st = native(sat_trace, False)
     sat_rate = st.completed / st.wall_s
-    points = [{"load": "saturation", "req_per_s": round(sat_rate, 1),
-               "numbers_per_s": round(st.numbers / st.wall_s, 1),
-               "p50_ms": round(st.percentile(50) * 1e3, 3), "p99_ms": round(st.percentile(99) * 1e3, 3)}]
+    points = [point("saturation", st)]
     for frac in (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
         lam = frac * sat_rate
-        num = int(min(12000, max(300, lam * 1.5)))
+        num = int(min(40000, max(500, lam * 1.5)))
         trace = I.serving_trace(num, rate_per_s=lam, num_gens=G, seed=6000 + int(frac * 100))
-        s = run(trace, True)
-        points.append({"load": frac, "req_per_s": round(lam, 1), "requests": num, "completed": s.completed,
-                       "numbers_per_s": round(s.numbers / s.wall_s, 1),
-                       "p50_ms": round(s.percentile(50) * 1e3, 3), "p99_ms": round(s.percentile(99) * 1e3, 3)})
+        s = native(trace, True)
+        points.append(point(frac, s, lam, num))
         log(f"serving load {frac}: {points[-1]}")
+    # the Python loop at the rate the native loop sustained at 0.5 load, for comparison
+    lam = 0.5 * sat_rate
+    trace = I.serving_trace(int(min(12000, max(500, lam * 1.5))), rate_per_s=lam, num_gens=G, seed=6050)
+    srv = serve.Server(serve.GpuExecutor(batch), mem_budget_bytes=arena, chunk=chunk, depth=2, keep_outputs=False)
+    py = point(0.5, srv.run(trace, realtime=True), lam, len(trace))
     batch.close()
     torch.cuda.empty_cache()
-    return {"generators": G, "chunk": 1 << 18, "mem_budget_GiB": 8, "sigma": 1.5, "points": points}
+    return {"generators": G, "chunk": chunk, "arena_GiB": arena >> 30, "sigma": 1.5, "loop": "native",
+            "points": points, "python_loop_at_0.5": py}
 
 
 def main():

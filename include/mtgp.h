@@ -300,6 +300,52 @@ typedef struct {
 int mtgp_search_params(uint32_t mexp, uint32_t id, uint64_t seed, uint64_t max_draws, uint32_t threads,
                        mtgp_param_set *out, mtgp_search_stats *stats);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop over a batch's resident
+ * generators, for callers that receive stream requests over time. Requests
+ * are admitted in arrival order while their outputs (4n bytes, 256-byte
+ * aligned) fit a caller-owned device arena (first fit; a request that does
+ * not fit waits, and so do the ones behind it). Each mtgp_server_poll
+ * retires ticks whose completion event has fired, admits what fits, and
+ * launches ticks on `stream` while fewer than `depth` are in flight. A tick
+ * advances every generator with admitted work by up to `chunk` outputs of
+ * its oldest unfinished request, in one batched launch; requests of one
+ * generator are served in arrival order, so each result is exactly the
+ * stream segment it would get alone. A completed request's outputs stay in
+ * the arena until mtgp_server_release. The batch and the arena must outlive
+ * the server; other calls on the batch must not run concurrently with it.
+ * Not thread-safe. Create returns NULL for a NULL batch or arena, an arena
+ * below 256 bytes or not 256-byte aligned, chunk 0 or depth 0 (chunk is
+ * rounded down to even).
+ * ------------------------------------------------------------------------- */
+typedef struct mtgp_server mtgp_server_t;
+typedef struct {
+    uint64_t rid;      /* the id given at submit */
+    uint64_t offset;   /* byte offset of its n outputs in the arena */
+    uint64_t n;
+} mtgp_completion;
+mtgp_server_t *mtgp_server_create(mtgp_batch_t *b, void *arena, uint64_t arena_bytes, uint64_t chunk,
+                                  uint32_t depth, void *stream);
+typedef struct {
+    uint64_t rid;      /* caller's id; ids of unreleased requests must be distinct */
+    uint32_t gen;
+    uint32_t kind;
+    uint64_t n;
+} mtgp_server_request;
+/* Queue `count` requests in arrival order. All-or-nothing: MTGP_EINVAL if
+ * any has a bad generator or kind, n = 0, an odd n for normals, or outputs
+ * larger than the arena. */
+int mtgp_server_submit(mtgp_server_t *s, const mtgp_server_request *reqs, uint32_t count);
+/* One scheduling step; writes up to max_done completions (oldest first; the
+ * rest are returned by later polls) and their count. MTGP_EDEVICE on a HIP
+ * error. */
+int mtgp_server_poll(mtgp_server_t *s, mtgp_completion *done, uint32_t max_done, uint32_t *n_done);
+/* Return completed requests' arena space; ids that are unknown or not yet
+ * finished are skipped and make the call return MTGP_EINVAL. */
+int mtgp_server_release(mtgp_server_t *s, const uint64_t *rids, uint32_t count);
+int mtgp_server_pending(const mtgp_server_t *s, uint64_t *waiting, uint64_t *active, uint32_t *inflight);
+void mtgp_server_destroy(mtgp_server_t *s);   /* NULL-safe; waits for in-flight ticks */
+
 #ifdef __cplusplus
 }
 #endif

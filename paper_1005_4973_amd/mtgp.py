@@ -47,6 +47,14 @@ class SearchStatsC(ctypes.Structure):
                 ("sieve_passed", ctypes.c_uint64), ("seconds", ctypes.c_double)]
 
 
+class ServerRequestC(ctypes.Structure):
+    _fields_ = [("rid", ctypes.c_uint64), ("gen", ctypes.c_uint32), ("kind", ctypes.c_uint32), ("n", ctypes.c_uint64)]
+
+
+class CompletionC(ctypes.Structure):
+    _fields_ = [("rid", ctypes.c_uint64), ("offset", ctypes.c_uint64), ("n", ctypes.c_uint64)]
+
+
 class TuningC(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("threads", ctypes.c_int), ("spl", ctypes.c_int),
                 ("split_rounds", ctypes.c_uint32), ("ms", ctypes.c_float), ("trials", ctypes.c_uint32)]
@@ -90,6 +98,15 @@ _SIGNATURES = {
     "mtgp_plan_launch_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "mtgp_batch_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_server_create": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.c_uint32, ctypes.c_void_p]),
+    "mtgp_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CompletionC), ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_uint32)]),
+    "mtgp_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_server_pending": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32)]),
+    "mtgp_server_destroy": (None, [ctypes.c_void_p]),
     "mtgp_search_params": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                           ctypes.c_uint32, ctypes.POINTER(ParamSetC), ctypes.POINTER(SearchStatsC)]),
     "mtgp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p,

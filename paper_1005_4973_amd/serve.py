@@ -15,7 +15,9 @@ consecutive chunks of one generator in sequence); completion is detected with
 events and a request's latency is its completion time minus its arrival time.
 
 The executor interface (launch / ready / wait) lets tests drive the same
-scheduler with a CPU executor.
+scheduler with a CPU executor. NativeServer runs the same policy in the
+library (mtgp_server_*), with the request bookkeeping, admission and tick
+building in C++; Python only feeds arrivals and collects completions.
 """
 from __future__ import annotations
 
@@ -251,3 +253,126 @@ class Server:
         span = trace[-1][0] if (realtime and trace) else 0.0
         rate = len(trace) / span if span > 0 else math.inf
         return ServeStats(rate, len(done), len(self.rejected), sum(r.n for r in done), wall, lat)
+
+
+SERVER_REQUEST_DTYPE = [("rid", "<u8"), ("gen", "<u4"), ("kind", "<u4"), ("n", "<u8")]
+COMPLETION_DTYPE = [("rid", "<u8"), ("offset", "<u8"), ("n", "<u8")]
+
+
+class NativeServer:
+    """The library's request loop (mtgp_server_*) over a batch, with a device
+    output arena of `arena_bytes` (the admission budget)."""
+
+    def __init__(self, batch, arena_bytes: int = 8 << 30, chunk: int = 1 << 18, depth: int = 2,
+                 stream=None, max_report: int = 1 << 16):
+        import numpy as np
+        import torch
+        from . import mtgp
+        self.np, self.torch, self.mtgp = np, torch, mtgp
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.arena = torch.empty(arena_bytes // 4, dtype=torch.int32, device="cuda")
+        L = mtgp.lib()
+        self._h = L.mtgp_server_create(batch._h, self.arena.data_ptr(), arena_bytes, chunk, depth,
+                                       mtgp._stream_ptr(self.stream))
+        if not self._h:
+            raise mtgp.MTGPError(mtgp.MTGP_EINVAL, "mtgp_server_create")
+        self._done = np.zeros(max_report, dtype=COMPLETION_DTYPE)
+        self._ndone = __import__("ctypes").c_uint32(0)
+
+    def submit(self, reqs):
+        """reqs: numpy array of SERVER_REQUEST_DTYPE, in arrival order."""
+        if len(reqs):
+            self.mtgp._check(self.mtgp.lib().mtgp_server_submit(self._h, reqs.ctypes.data, len(reqs)),
+                             "mtgp_server_submit")
+
+    def poll(self):
+        """One scheduling step; returns completions (numpy COMPLETION_DTYPE)."""
+        import ctypes
+        L = self.mtgp.lib()
+        ptr = self._done.ctypes.data_as(ctypes.POINTER(self.mtgp.CompletionC))
+        self.mtgp._check(L.mtgp_server_poll(self._h, ptr, len(self._done), ctypes.byref(self._ndone)),
+                         "mtgp_server_poll")
+        return self._done[: self._ndone.value].copy()
+
+    def release(self, rids):
+        rids = self.np.ascontiguousarray(rids, dtype=self.np.uint64)
+        if len(rids):
+            self.mtgp._check(self.mtgp.lib().mtgp_server_release(self._h, rids.ctypes.data, len(rids)),
+                             "mtgp_server_release")
+
+    def output(self, offset: int, n: int):
+        """A completed request's outputs: a view of the arena (valid until released)."""
+        return self.arena[offset // 4: offset // 4 + n]
+
+    def pending(self):
+        """(waiting, active, in-flight ticks) inside the library's loop."""
+        import ctypes
+        w, a, f = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint32(0)
+        self.mtgp._check(self.mtgp.lib().mtgp_server_pending(self._h, ctypes.byref(w), ctypes.byref(a),
+                                                            ctypes.byref(f)), "mtgp_server_pending")
+        return w.value, a.value, f.value
+
+    def run(self, trace: Sequence[Tuple[float, int, int, int]], realtime: bool = True, keep: bool = False,
+            on_complete: Optional[Callable[[int, object], None]] = None, poll_s: float = 20e-6,
+            clock: Callable[[], float] = time.perf_counter) -> ServeStats:
+        """Like Server.run. Each completed request's outputs are handed to
+        on_complete(rid, arena view) if given, then released, unless keep (then
+        self.kept maps rid -> (offset, n) and the caller releases them; a trace
+        whose kept outputs outgrow the arena raises instead of waiting)."""
+        np = self.np
+        arrival = np.array([t[0] if realtime else 0.0 for t in trace], dtype=np.float64)
+        reqs = np.zeros(len(trace), dtype=SERVER_REQUEST_DTYPE)
+        reqs["rid"] = np.arange(len(trace))
+        reqs["gen"] = [t[1] for t in trace]
+        reqs["n"] = [t[2] for t in trace]
+        reqs["kind"] = [t[3] for t in trace]
+        t_done = np.full(len(trace), np.nan)
+        self.kept = {}
+        t0 = clock()
+        i = 0
+        outstanding = 0
+        while i < len(trace) or outstanding > 0:
+            now = clock() - t0
+            j = int(np.searchsorted(arrival, now, side="right")) if realtime else len(trace)
+            if j > i:
+                self.submit(reqs[i:j])
+                outstanding += j - i
+                i = j
+            done = self.poll()
+            if len(done):
+                t_done[done["rid"].astype(np.int64)] = clock() - t0
+                outstanding -= len(done)
+                if on_complete is not None:
+                    for c in done:
+                        on_complete(int(c["rid"]), self.output(int(c["offset"]), int(c["n"])))
+                if keep:
+                    for c in done:
+                        self.kept[int(c["rid"])] = (int(c["offset"]), int(c["n"]))
+                else:
+                    self.release(done["rid"])
+            elif outstanding > 0:
+                if keep:
+                    waiting, active, inflight = self.pending()
+                    if waiting and not active and not inflight:
+                        raise RuntimeError("the arena is full of kept outputs: release some or use a larger arena")
+                time.sleep(poll_s)                            # work on the device: poll again shortly
+            elif i < len(trace):
+                time.sleep(max(0.0, arrival[i] - (clock() - t0)))   # idle until the next arrival
+        wall = clock() - t0
+        ok = ~np.isnan(t_done)
+        lat = list((t_done - arrival)[ok])
+        span = trace[-1][0] if (realtime and trace) else 0.0
+        rate = len(trace) / span if span > 0 else math.inf
+        return ServeStats(rate, int(ok.sum()), 0, int(reqs["n"][ok].sum()), wall, lat)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.mtgp.lib().mtgp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -63,3 +63,42 @@ def test_serving_alone_vs_mix(env):
         for (rid, _), r in zip(sub, sorted(s1.completed, key=lambda r: r.rid)):
             np.testing.assert_array_equal(bits(r.out), mixed[rid])
         b1.close()
+
+
+def test_native_server_alone_vs_mix(env):
+    """The library's request loop: a mixed trace gives every request the
+    oracle's stream segment for its generator in arrival order, including
+    normals (within the normal kind's tolerance) and a small arena that makes
+    requests wait for space."""
+    torch, mtgp, serve = env
+    G = 256
+    params = I.draw_param_sets([11213] * G, 5300)
+    seeds = I.state_seeds(G)
+    trace = I.serving_trace(800, rate_per_s=40000.0, num_gens=G, seed=5400, median_log2=12, sigma=1.5,
+                            lo_log2=4, hi_log2=17)
+    # a few busy generators; every fifth request asks for normals (even n)
+    trace = [(t, g % 24 if i % 3 == 0 else g, (n + 1) // 2 * 2 if i % 5 == 0 else n, 3 if i % 5 == 0 else k)
+             for i, (t, g, n, k) in enumerate(trace)]
+    say(f"native server trace: {len(trace)} requests")
+    b = mtgp.Batch(params, seeds)
+    srv = serve.NativeServer(b, arena_bytes=8 << 20, chunk=1 << 13, depth=2)
+    got = {}
+    st = srv.run(trace, realtime=True, on_complete=lambda rid, out: got.__setitem__(rid, bits(out)))
+    assert st.completed == len(trace) and len(got) == len(trace)
+    assert srv.pending() == (0, 0, 0)
+    states = {}
+    for rid, (_, g, n, k) in enumerate(trace):
+        assert got[rid].size == n
+        st_g = states.setdefault(g, O.seed_state(seeds[g], params[g].mexp))
+        if k == 3:
+            z = got[rid].view(np.float32).astype(np.float64)
+            assert np.abs(z - O.normals(params[g], st_g, n)).max() <= 1.5e-5, f"rid={rid}"
+        else:
+            np.testing.assert_array_equal(got[rid], O.generate(params[g], st_g, n, k), err_msg=f"rid={rid}")
+    # keep mode: a trace whose kept outputs outgrow the arena raises instead of waiting forever
+    srv2 = serve.NativeServer(b, arena_bytes=1 << 20, chunk=1 << 13, depth=2)
+    with pytest.raises(RuntimeError):
+        srv2.run([(0.0, g, 1 << 17, 0) for g in range(4)], realtime=False, keep=True)
+    srv2.close()
+    srv.close()
+    b.close()
