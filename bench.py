@@ -68,30 +68,40 @@ def roof(nbytes, seconds):
     return {"GBs": round(a, 1), "frac_of_8TBs": round(a / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(params, n_per_gen, kinds, threads):
-    """The oracle on the host cores: one generator and kind per task."""
+def cpu_baseline(params, n_per_gen, kinds, threads, reps=30):
+    """The oracle on the host cores: one generator and kind per task, each
+    task producing `reps` chunks of the headline's per-generator length (the
+    workload's generators, kinds and lengths, about 10 s of wall time on 16
+    cores); plus single-core rates for the three periods."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     from paper_1005_4973_amd import inputs as I
 
-    # about 15 s of single-core oracle work: every generator, every kind,
-    # three times the per-generator length of one step
-    n = 3 * n_per_gen
     tasks = [(g, k) for g in range(len(params)) for k in kinds]
 
     def run(task):
         g, k = task
         st = O.seed_state(I.STATE_SEED_BASE + g, params[g].mexp)
-        O.generate(params[g], st, n, k)
-        return n
+        for _ in range(reps):
+            O.generate(params[g], st, n_per_gen, k)
+        return reps * n_per_gen
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
         total = sum(ex.map(run, tasks))
     dt = time.perf_counter() - t0
+    single = {}
+    for mexp in (11213, 23209, 44497):
+        ps = I.draw_param_sets([mexp], 7000 + mexp % 97)[0]
+        st = O.seed_state(1, mexp)
+        m = 1 << 24
+        t1 = time.perf_counter()
+        O.generate(ps, st, m, O.U32)
+        single[f"p{mexp}"] = round(m / (time.perf_counter() - t1) / 1e6, 1)
     return {"value": round(total / dt / 1e9, 4), "unit": "G numbers/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(params)} generators x {n} outputs x {len(kinds)} kinds "
-                      f"({total} numbers, {dt:.2f} s wall)"}
+            "sample": f"{len(params)} generators x {len(kinds)} kinds x {reps} chunks of {n_per_gen} outputs "
+                      f"({total} numbers, {dt:.2f} s wall on {threads} threads)",
+            "single_core_M_numbers_s": single}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mtgp_kernel_headline_128x4M_traffic.md")
@@ -178,6 +188,10 @@ def headline(args, torch, I, mtgp):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
+    # store-only ceiling: a torch fill of the same 2 GiB buffer
+    fill_ms = timed_ms(torch, lambda: out.fill_(7), reps=5)
+    store_gbs = 4 * G * n / fill_ms / 1e6
+
     numbers_per_step = G * n * len(kinds)
     gen_ms = [b.elapsed_time(c) for a, b, c in ev]
     prep_ms = [a.elapsed_time(b) for a, b, c in ev]
@@ -199,7 +213,9 @@ def headline(args, torch, I, mtgp):
                      "kernel": "mtgp_kernel<false> (persistent generation over jump-ahead segments)",
                      "avg_launch_ms": round(avg_gen_s * 1e3, 4),
                      "avg_prepare_ms": round(sum(prep_ms) / len(prep_ms), 4),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "store_ceiling_GBs": round(store_gbs, 1),
+                     "frac_of_store_ceiling": round(achieved / store_gbs, 4)},
     }
 
 
