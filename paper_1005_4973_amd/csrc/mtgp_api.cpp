@@ -33,9 +33,6 @@ constexpr uint32_t kMaxMexp = 65536;        // N <= 2048
 constexpr size_t kLdsPerCu = 160u * 1024u;  // gfx950 LDS per compute unit
 constexpr size_t kUnitLdsExtra = 64;        // table words ahead of each window
 constexpr uint32_t kWavesPerCu = 32;        // resident wavefront limit per CU used for sizing grids
-// A window this large (in words) takes more than half of a CU's LDS, so the
-// hardware places at most one such workgroup per CU.
-constexpr uint32_t kExclusiveWindow = 24000;
 
 uint32_t words_of(uint32_t mexp) { return (mexp + 31u) / 32u; }
 
@@ -388,14 +385,14 @@ void batch_free(mtgp_batch *b)
 {
     if (!b)
         return;
-    hipFree(b->d_recs);
-    hipFree(b->d_states);
-    hipFree(b->d_counters);
-    hipFree(b->d_items);
+    (void)hipFree(b->d_recs);
+    (void)hipFree(b->d_states);
+    (void)hipFree(b->d_counters);
+    (void)hipFree(b->d_items);
     if (b->h_items)
-        hipHostFree(b->h_items);
+        (void)hipHostFree(b->h_items);
     if (b->items_free)
-        hipEventDestroy(b->items_free);
+        (void)hipEventDestroy(b->items_free);
     delete b;
 }
 
@@ -405,15 +402,15 @@ void plan_free(mtgp_plan *p)
         return;
     for (int k = 0; k < 3; k++) {
         if (p->exec[k])
-            hipGraphExecDestroy(p->exec[k]);
+            (void)hipGraphExecDestroy(p->exec[k]);
         if (p->graph[k])
-            hipGraphDestroy(p->graph[k]);
+            (void)hipGraphDestroy(p->graph[k]);
     }
     if (p->capture)
-        hipStreamDestroy(p->capture);
-    hipFree(p->d_items);
-    hipFree(p->d_counters);
-    hipFree(p->d_jump_mem);
+        (void)hipStreamDestroy(p->capture);
+    (void)hipFree(p->d_items);
+    (void)hipFree(p->d_counters);
+    (void)hipFree(p->d_jump_mem);
     delete p;
 }
 
@@ -566,7 +563,7 @@ int ensure_annihilators(mtgp_batch *b, const std::vector<uint32_t> &gens)
         return MTGP_EDEVICE;
     if (hipMalloc(&d_raw, total * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&d_items, items.size() * sizeof(WorkItem)) != hipSuccess) {
-        hipFree(d_raw);
+        (void)hipFree(d_raw);
         return MTGP_ENOMEM;
     }
     for (size_t i = 0; i < todo.size(); i++) {
@@ -586,12 +583,12 @@ int ensure_annihilators(mtgp_batch *b, const std::vector<uint32_t> &gens)
             hipSuccess ||
         launch_generate(b->d_recs, b->d_states, d_items, (uint32_t)items.size(), nullptr, none, s, st) != hipSuccess ||
         hipMemcpyAsync(raw.data(), d_raw, total * sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+        (void)hipStreamSynchronize(st) != hipSuccess)
         rc = MTGP_EDEVICE;
     if (st)
-        hipStreamDestroy(st);
-    hipFree(d_items);
-    hipFree(d_raw);
+        (void)hipStreamDestroy(st);
+    (void)hipFree(d_items);
+    (void)hipFree(d_raw);
     if (rc != MTGP_OK)
         return rc;
     parallel_for(todo.size(), [&](size_t i) {
@@ -813,16 +810,16 @@ mtgp_t *mtgp_create(const mtgp_param_set *ps, uint32_t seed)
     seed_words(seed, N, words.data());
     if (hipMalloc(&g->d_rec, sizeof(GenRecord)) != hipSuccess ||
         hipMalloc(&g->d_state, N * sizeof(uint32_t)) != hipSuccess) {
-        hipFree(g->d_rec);
-        hipFree(g->d_state);
+        (void)hipFree(g->d_rec);
+        (void)hipFree(g->d_state);
         delete g;
         fail(MTGP_ENOMEM);
         return nullptr;
     }
     if (hipMemcpy(g->d_rec, &g->rec, sizeof(GenRecord), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(g->d_state, words.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(g->d_rec);
-        hipFree(g->d_state);
+        (void)hipFree(g->d_rec);
+        (void)hipFree(g->d_state);
         delete g;
         fail(MTGP_EDEVICE);
         return nullptr;
@@ -863,8 +860,8 @@ static int generate_split(mtgp_t *g, uint64_t n, void *out, hipStream_t s, uint3
         const bool ok = launch_generate(g->d_rec, g->d_state, nullptr, 1, nullptr, it, g->shape, s) == hipSuccess &&
                         hipMemcpyAsync(raw.data(), d_raw, raw.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s) ==
                             hipSuccess &&
-                        hipStreamSynchronize(s) == hipSuccess;
-        hipFree(d_raw);
+                        (void)hipStreamSynchronize(s) == hipSuccess;
+        (void)hipFree(d_raw);
         if (!ok)
             return MTGP_EDEVICE;
         g->psi = orbit_annihilator(raw.data(), raw.size(), N, g->ps.mexp);
@@ -883,7 +880,7 @@ static int generate_split(mtgp_t *g, uint64_t n, void *out, hipStream_t s, uint3
         // buffers and jump polynomials for this segment length
         if (hipStreamSynchronize(g->last) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             return MTGP_EDEVICE;
-        hipFree(g->d_split);
+        (void)hipFree(g->d_split);
         g->d_split = nullptr;
         g->split_J = 0;
         g->split_S = 0;
@@ -929,7 +926,7 @@ static int generate_split(mtgp_t *g, uint64_t n, void *out, hipStream_t s, uint3
             hipMemset(g->d_counters, 0, 2 * sizeof(uint32_t)) != hipSuccess)
             return MTGP_EDEVICE;
         if (g->h_items)
-            hipHostFree(g->h_items);
+            (void)hipHostFree(g->h_items);
         g->h_items = nullptr;
         if (hipHostMalloc(reinterpret_cast<void **>(&g->h_items), (size_t)S * sizeof(WorkItem)) != hipSuccess)
             return MTGP_ENOMEM;
@@ -1049,14 +1046,14 @@ void mtgp_destroy(mtgp_t *g)
 {
     if (!g)
         return;
-    hipStreamSynchronize(g->last);
-    hipFree(g->d_rec);
-    hipFree(g->d_state);
-    hipFree(g->d_split);
+    (void)hipStreamSynchronize(g->last);
+    (void)hipFree(g->d_rec);
+    (void)hipFree(g->d_state);
+    (void)hipFree(g->d_split);
     if (g->h_items)
-        hipHostFree(g->h_items);
+        (void)hipHostFree(g->h_items);
     if (g->items_free)
-        hipEventDestroy(g->items_free);
+        (void)hipEventDestroy(g->items_free);
     delete g;
 }
 
@@ -1187,7 +1184,7 @@ void mtgp_batch_destroy(mtgp_batch_t *b)
 {
     if (!b)
         return;
-    hipStreamSynchronize(b->last);
+    (void)hipStreamSynchronize(b->last);
     batch_free(b);
 }
 
@@ -1210,9 +1207,9 @@ int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
         b->items_pending = false;
     }
     if (nitems > b->item_cap) {
-        hipFree(b->d_items);
+        (void)hipFree(b->d_items);
         if (b->h_items)
-            hipHostFree(b->h_items);
+            (void)hipHostFree(b->h_items);
         b->d_items = nullptr;
         b->h_items = nullptr;
         b->item_cap = 0;
@@ -1430,7 +1427,7 @@ void mtgp_plan_destroy(mtgp_plan_t *p)
     if (!p)
         return;
     if (p->b)
-        hipStreamSynchronize(p->b->last);
+        (void)hipStreamSynchronize(p->b->last);
     plan_free(p);
 }
 
@@ -1447,7 +1444,7 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     if (hipMalloc(&d_save, b->state_words * sizeof(uint32_t)) != hipSuccess)
         return fail(MTGP_ENOMEM);
     if (hipMemcpy(d_save, b->d_states, b->state_words * sizeof(uint32_t), hipMemcpyDeviceToDevice) != hipSuccess) {
-        hipFree(d_save);
+        (void)hipFree(d_save);
         return fail(MTGP_EDEVICE);
     }
     const std::vector<uint64_t> consumed = b->consumed;
@@ -1456,7 +1453,7 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     const uint32_t had_split = b->split_rounds;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        hipFree(d_save);
+        (void)hipFree(d_save);
         return fail(MTGP_EDEVICE);
     }
 
@@ -1489,7 +1486,7 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
         device_ok = device_ok &&
                     hipMemcpyAsync(b->d_states, d_save, b->state_words * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                                    s) == hipSuccess &&
-                    hipStreamSynchronize(s) == hipSuccess;
+                    (void)hipStreamSynchronize(s) == hipSuccess;
         b->consumed = consumed;
     };
 
@@ -1541,9 +1538,9 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
         trial(c);
         tried.push_back(c);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(d_save);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d_save);
     const Cand win = best_of();
     if (!device_ok || win.ms <= 0) {
         b->have_override = had_override;

@@ -285,11 +285,11 @@ void mtgp_server_destroy(mtgp_server_t *s)
     if (!s)
         return;
     for (Tick &t : s->inflight) {
-        hipEventSynchronize(t.done);
+        (void)hipEventSynchronize(t.done);
         s->spare_events.push_back(t.done);
     }
     for (hipEvent_t e : s->spare_events)
-        hipEventDestroy(e);
+        (void)hipEventDestroy(e);
     for (Req *r : s->waiting)
         delete r;
     for (auto &kv : s->active)
