@@ -583,7 +583,7 @@ int ensure_annihilators(mtgp_batch *b, const std::vector<uint32_t> &gens)
             hipSuccess ||
         launch_generate(b->d_recs, b->d_states, d_items, (uint32_t)items.size(), nullptr, none, s, st) != hipSuccess ||
         hipMemcpyAsync(raw.data(), d_raw, total * sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        (void)hipStreamSynchronize(st) != hipSuccess)
+        hipStreamSynchronize(st) != hipSuccess)
         rc = MTGP_EDEVICE;
     if (st)
         (void)hipStreamDestroy(st);
@@ -860,7 +860,7 @@ static int generate_split(mtgp_t *g, uint64_t n, void *out, hipStream_t s, uint3
         const bool ok = launch_generate(g->d_rec, g->d_state, nullptr, 1, nullptr, it, g->shape, s) == hipSuccess &&
                         hipMemcpyAsync(raw.data(), d_raw, raw.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s) ==
                             hipSuccess &&
-                        (void)hipStreamSynchronize(s) == hipSuccess;
+                        hipStreamSynchronize(s) == hipSuccess;
         (void)hipFree(d_raw);
         if (!ok)
             return MTGP_EDEVICE;
@@ -1486,7 +1486,7 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
         device_ok = device_ok &&
                     hipMemcpyAsync(b->d_states, d_save, b->state_words * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                                    s) == hipSuccess &&
-                    (void)hipStreamSynchronize(s) == hipSuccess;
+                    hipStreamSynchronize(s) == hipSuccess;
         b->consumed = consumed;
     };
 
