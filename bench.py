@@ -18,7 +18,8 @@ The same JSON line also reports:
                   graph-captured persistent launch vs one launch per request
   large_states    256 generators at p = 23209 and at p = 44497, 2^24 uint32 each
   normals         the headline generators, 2^22 Box-Muller normals each (float32)
-  param_search    host-side search for full-period parameter sets (p = 4423, 11213)
+  param_search    host-side search for full-period parameter sets (p = 4423, 11213) and
+                  the dimension of equidistribution k(v), Delta of one found set
   single_stream   one MTGP-11213 generator, 2^20 uint32 per eager call, unsplit
                   and split into jump-ahead segments
   serving         65536 resident MTGP-11213 states behind the library's native
@@ -304,10 +305,20 @@ def param_search(torch, I, mtgp):
     search took 338 s per MTGP-11213 set on average (context only)."""
     threads = min(16, len(os.sched_getaffinity(0)))
     runs = []
+    found = {}
     for mexp, ident in ((4423, 1), (11213, 1), (11213, 4)):
-        _, st = mtgp.search_params(mexp, id=ident, seed=mexp, threads=threads)
+        ps, st = mtgp.search_params(mexp, id=ident, seed=mexp, threads=threads)
         runs.append({"mexp": mexp, "id": ident, "draws": st["draws"], "seconds": st["seconds"]})
-    return {"threads": threads, "runs": runs}
+        found[(mexp, ident)] = ps
+    # dimension of equidistribution (section 3.4) of a found set, tempered and
+    # not: one core, host only
+    ps = found[(11213, 1)]
+    equi = {"mexp": 11213, "id": 1}
+    for name, tempered in (("tempered", True), ("untempered", False)):
+        t0 = time.perf_counter()
+        k, delta = mtgp.equidistribution(ps, tempered=tempered)
+        equi[name] = {"delta": delta, "k_min": min(k), "seconds": round(time.perf_counter() - t0, 2)}
+    return {"threads": threads, "runs": runs, "equidistribution": equi}
 
 
 def single_stream(torch, I, mtgp):

@@ -301,6 +301,26 @@ int mtgp_search_params(uint32_t mexp, uint32_t id, uint64_t seed, uint64_t max_d
                        mtgp_param_set *out, mtgp_search_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * Dimension of equidistribution (section 3.4): k[v-1] = k(v) for v = 1 ..
+ * vmax, the largest k such that the v MSBs of k consecutive outputs are
+ * k-dimensionally equidistributed over the period, and *delta (may be NULL)
+ * = sum over v <= vmax of floor(p/v) - k(v), the total dimension defect
+ * (vmax = 32 gives the paper's Delta). `tempered` selects the uint32
+ * outputs (the float [1,2) and [0,1) outputs carry their 23 MSBs, so k(v)
+ * for v <= 23 is theirs too); 0 selects the untempered words x_{i+N}.
+ * Computed on the host by lattice reduction over F2[t] (the dual form of
+ * the lattice methods section 5 uses); no device is used. The definition
+ * needs period 2^p - 1: the set must pass the library's checks, mexp must be
+ * a prime in 67..65536 and the characteristic polynomial irreducible of
+ * degree mexp (what mtgp_search_params returns), else MTGP_EINVAL.
+ * Arguments: ps and k non-NULL (k holds vmax words), 1 <= vmax <= 32.
+ * Returns MTGP_OK, MTGP_EINVAL or MTGP_ENOMEM. The time grows about as
+ * vmax^2 mexp^2.
+ * ------------------------------------------------------------------------- */
+int mtgp_equidistribution(const mtgp_param_set *ps, uint32_t tempered, uint32_t vmax, uint32_t *k,
+                          uint32_t *delta);
+
+/* ---------------------------------------------------------------------------
  * Serving: a continuous-batching request loop over a batch's resident
  * generators, for callers that receive stream requests over time. Requests
  * are admitted in arrival order while their outputs (4n bytes, 256-byte

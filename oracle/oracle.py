@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from types import SimpleNamespace
 from typing import Sequence
 
 import numpy as np
@@ -166,3 +167,79 @@ def irreducible_prime_degree(phi: np.ndarray) -> bool:
     if rc < 0:
         raise ValueError("bad polynomial")
     return rc == 1
+
+
+# ---------------------------------------------------------------------------
+# Dimension of equidistribution by its definition (section 3.4), for small p.
+#
+# For a generator of period 2^p - 1 (every nonzero state on one orbit), the
+# v MSBs of k consecutive outputs are k-dimensionally equidistributed exactly
+# when the map from the p-bit state to those k*v bits is onto, i.e. when the
+# k*v output-bit functionals are linearly independent over F2. The functional
+# of bit b of output i is read off the outputs of the p unit states.
+# Pure Python Gaussian elimination: for p up to a few hundred.
+# ---------------------------------------------------------------------------
+
+
+def state_bit_positions(mexp: int):
+    """(word, bit) of the p state bits: the 32 - r high bits of x_0 (the only
+    ones the recursion reads, through the mask) and every bit of x_1 .. x_{N-1}."""
+    N = nwords(mexp)
+    r = 32 * N - mexp
+    return [(0, b) for b in range(r, 32)] + [(w, b) for w in range(1, N) for b in range(32)]
+
+
+def unit_state_outputs(ps, n: int, tempered: bool = True) -> np.ndarray:
+    """cols[s, i] = uint32 output i from the s-th unit state. Untempered
+    outputs are the raw words x_{i+N}: the same recursion with a zero
+    tempering table."""
+    if not tempered:
+        ps = SimpleNamespace(mexp=ps.mexp, pos=ps.pos, sh1=ps.sh1, sh2=ps.sh2,
+                             param_tbl=tuple(ps.param_tbl), temper_tbl=(0,) * 16)
+    pos = state_bit_positions(ps.mexp)
+    cols = np.zeros((len(pos), n), dtype=np.uint32)
+    for s, (w, b) in enumerate(pos):
+        st = np.zeros(nwords(ps.mexp), dtype=np.uint32)
+        st[w] = np.uint32(1 << b)
+        cols[s] = generate(ps, st, n, U32)
+    return cols
+
+
+def equidistribution_by_rank(cols: np.ndarray, width: int, vmax: int):
+    """k(v) for v = 1 .. vmax of a full-period F2-linear generator whose
+    `width`-bit outputs from the p unit states are cols[s, i]: the largest k
+    such that the bit functionals of the v MSBs of outputs 0 .. k-1 are
+    independent (k is capped at the number of outputs given; give p + 1)."""
+    p, kmax = cols.shape
+    weights = [1 << s for s in range(p)]
+
+    def functional(i, j):   # bit width-1-j of output i, as a p-bit integer over the unit states
+        bits = (cols[:, i] >> np.uint32(width - 1 - j)) & np.uint32(1)
+        return sum(w for w, x in zip(weights, bits.tolist()) if x)
+
+    rows = {}
+    ks = []
+    for v in range(1, vmax + 1):
+        pivots = {}
+        k = kmax
+        for i in range(kmax):
+            dependent = False
+            for j in range(v):
+                if (i, j) not in rows:
+                    rows[(i, j)] = functional(i, j)
+                x = rows[(i, j)]
+                while x:
+                    top = x.bit_length() - 1
+                    if top in pivots:
+                        x ^= pivots[top]
+                    else:
+                        pivots[top] = x
+                        break
+                if x == 0:
+                    dependent = True
+                    break
+            if dependent:
+                k = i
+                break
+        ks.append(k)
+    return ks

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libmtgp.so")
 SOURCES = [os.path.join(CSRC, "mtgp_kernels.hip"), os.path.join(CSRC, "mtgp_api.cpp"),
-           os.path.join(CSRC, "mtgp_f2.cpp"), os.path.join(CSRC, "mtgp_dc.cpp"), os.path.join(CSRC, "mtgp_serve.cpp")]
+           os.path.join(CSRC, "mtgp_f2.cpp"), os.path.join(CSRC, "mtgp_dc.cpp"), os.path.join(CSRC, "mtgp_serve.cpp"),
+           os.path.join(CSRC, "mtgp_equidist.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

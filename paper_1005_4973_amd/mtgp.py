@@ -109,6 +109,8 @@ _SIGNATURES = {
     "mtgp_server_destroy": (None, [ctypes.c_void_p]),
     "mtgp_search_params": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                           ctypes.c_uint32, ctypes.POINTER(ParamSetC), ctypes.POINTER(SearchStatsC)]),
+    "mtgp_equidistribution": (ctypes.c_int, [ctypes.POINTER(ParamSetC), ctypes.c_uint32, ctypes.c_uint32,
+                                              ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
     "mtgp_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p,
                                            ctypes.c_uint32, ctypes.POINTER(TuningC)]),
     "mtgp_plan_destroy": (None, [ctypes.c_void_p]),
@@ -168,6 +170,17 @@ def search_params(mexp: int, id: int = 0, seed: int = 1, max_draws: int = 1 << 2
     stats = {"draws": st.draws, "evaluated": st.evaluated, "full_degree": st.full_degree,
              "sieve_passed": st.sieve_passed, "seconds": round(st.seconds, 3)}
     return FoundParams(p.mexp, p.pos, p.sh1, p.sh2, tuple(p.param_tbl), tuple(p.temper_tbl)), stats
+
+
+def equidistribution(ps, tempered: bool = True, vmax: int = 32):
+    """Dimensions of equidistribution k(1) .. k(vmax) (section 3.4) of a
+    full-period parameter set, and the total dimension defect over them
+    (mtgp_equidistribution; host only). Returns (list of k(v), delta)."""
+    k = (ctypes.c_uint32 * vmax)()
+    d = ctypes.c_uint32()
+    rc = lib().mtgp_equidistribution(ctypes.byref(_param_c(ps)), 1 if tempered else 0, vmax, k, ctypes.byref(d))
+    _check(rc, "mtgp_equidistribution")
+    return list(k), int(d.value)
 
 
 def _param_c(ps) -> ParamSetC:
