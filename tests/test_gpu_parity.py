@@ -240,6 +240,31 @@ def test_launch_shapes_parity(M):
     b.close()
 
 
+def test_wide_workgroups_long_streams(M):
+    """Workgroups wider than N - M: the wavefronts past the round width skip
+    its work and only meet the barriers, through many rounds, window
+    compactions and a partial last round."""
+    import torch
+    params = I.draw_param_sets([11213, 11213, 521], 66, I.M_POLICY_WIDE) + I.draw_param_sets([23209], 67)
+    seeds = I.state_seeds(len(params))
+    for threads in (512, 1024):
+        say(f"threads {threads}")
+        b = M.Batch(params, seeds)
+        b.set_launch(0, threads, 1, 0, 0)
+        states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+        for n in (300007, 4099):
+            reqs = [(g, g % 3, n) for g in range(len(params))]
+            bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in reqs]
+            b.generate([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+            torch.cuda.synchronize()
+            for (g, k, n), buf in zip(reqs, bufs):
+                ref = O.generate(params[g], states[g], n, k)
+                np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"threads={threads} gen={g} n={n}")
+        for g in range(len(params)):
+            np.testing.assert_array_equal(b.get_state(g)[0], states[g])
+        b.close()
+
+
 def test_outputs_at_addresses_with_bit31_set(M):
     """Output windows whose device address has bit 31 of its low word set, in
     both launch forms (regression: the low half of the address must be
