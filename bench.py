@@ -28,11 +28,12 @@ The same JSON line also reports:
                   (median 2^16, sigma 1.5, clipped to [2^10, 2^26]):
                   p50/p99 latency and sustained numbers/s
 `value` is numbers/s with states and parameters resident in HBM when the
-timed region starts.
+timed region starts. The sections time a launch or replay with HIP events:
+the median of 10 after 3 untimed ones (the plain one-launch-per-request
+baseline runs once, by wall clock).
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -133,10 +134,12 @@ def measured_traffic(tuning):
     return int(fields["traffic_bytes_per_launch"].strip())
 
 
-def timed_ms(torch, fn, reps=3):
-    fn()
+def timed_ms(torch, fn, reps=10, warmup=3):
+    """Median over `reps` event-timed calls after `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
-    best = math.inf
+    times = []
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -144,8 +147,10 @@ def timed_ms(torch, fn, reps=3):
         fn()
         e1.record()
         torch.cuda.synchronize()
-        best = min(best, e0.elapsed_time(e1))
-    return best
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    mid = len(times) // 2
+    return times[mid] if len(times) % 2 else 0.5 * (times[mid - 1] + times[mid])
 
 
 # ---------------------------------------------------------------------------
@@ -190,7 +195,7 @@ def headline(args, torch, I, mtgp):
     dt = time.perf_counter() - t0
 
     # store-only ceiling: a torch fill of the same 2 GiB buffer
-    fill_ms = timed_ms(torch, lambda: out.fill_(7), reps=5)
+    fill_ms = timed_ms(torch, lambda: out.fill_(7))
     store_gbs = 4 * G * n / fill_ms / 1e6
 
     numbers_per_step = G * n * len(kinds)
@@ -236,7 +241,7 @@ def batched_uneven(torch, I, mtgp):
     tuning = batch.autotune(rq, reps=2)
     tune_s = time.perf_counter() - t0
     plan = batch.plan(rq)
-    ms_b = timed_ms(torch, lambda: plan.launch(), reps=3)
+    ms_b = timed_ms(torch, lambda: plan.launch())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.generate_plain(rq)
@@ -267,7 +272,7 @@ def large_states(torch, I, mtgp):
         tuning = batch.autotune(rq, reps=2)
         tune_s = time.perf_counter() - t0
         plan = batch.plan(rq)
-        ms = timed_ms(torch, lambda: plan.launch(), reps=3)
+        ms = timed_ms(torch, lambda: plan.launch())
         plan.close()
         batch.close()
         del out
@@ -289,7 +294,7 @@ def normals(torch, I, mtgp):
     rq = [(g, mtgp.KIND_NORMAL_FLOAT32, n, out.data_ptr() + 4 * g * n) for g in range(G)]
     tuning = batch.autotune(rq, reps=2)
     plan = batch.plan(rq)
-    ms = timed_ms(torch, lambda: plan.launch(), reps=5)
+    ms = timed_ms(torch, lambda: plan.launch())
     plan.close()
     batch.close()
     del out
@@ -329,13 +334,13 @@ def single_stream(torch, I, mtgp):
     (ps,), n = I.single_stream()
     g = mtgp.Generator(ps, 1234)
     out = torch.empty(n, dtype=torch.int32, device="cuda")
-    ms = timed_ms(torch, lambda: g.generate(n, I.KIND_U32, out=out), reps=5)
+    ms = timed_ms(torch, lambda: g.generate(n, I.KIND_U32, out=out))
     g.set_split(16)
     t0 = time.perf_counter()
     g.generate(n, I.KIND_U32, out=out)
     torch.cuda.synchronize()
     first_s = time.perf_counter() - t0
-    ms_split = timed_ms(torch, lambda: g.generate(n, I.KIND_U32, out=out), reps=5)
+    ms_split = timed_ms(torch, lambda: g.generate(n, I.KIND_U32, out=out))
     g.close()
     return {"M": ps.pos, "numbers": n, "ms": round(ms, 4), "G_numbers_s": round(n / ms / 1e6, 3),
             "split_16_rounds": {"ms": round(ms_split, 4), "G_numbers_s": round(n / ms_split / 1e6, 3),
