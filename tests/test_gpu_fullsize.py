@@ -1,0 +1,144 @@
+"""Parity at the workloads' full sizes, in the configurations the benchmark
+times: autotuned jump-ahead plans for the 128 x 2^22 headline (every output
+of every kind), the 256 x 2^24 large-state batches and the 4096-request
+uneven batch (complete streams of sampled generators, the longest among
+them). The oracle runs on host threads (its C calls release the GIL).
+"""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1005_4973_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1005_4973_amd import mtgp
+    mtgp.lib()
+    return mtgp
+
+
+def pool():
+    return ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4))
+
+
+def device_words(out, start, n):
+    """n uint32 words of a device int32 tensor from word `start`."""
+    return out[start:start + n].cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.timeout(600)
+def test_headline_tuned_plans_full_size(M):
+    """128 MTGP-11213 generators x 2^22 as uint32, float [1,2), float [0,1):
+    the tuned split plans, replayed twice; all outputs compared."""
+    import torch
+    params, n = I.independent_128()
+    G = len(params)
+    seeds = I.state_seeds(G)
+    kinds = (I.KIND_U32, I.KIND_F12, I.KIND_F01)
+    b = M.Batch(params, seeds)
+    outs = {k: torch.empty(G * n, dtype=torch.int32, device="cuda") for k in kinds}
+    reqs = {k: [(g, k, n, outs[k].data_ptr() + 4 * g * n) for g in range(G)] for k in kinds}
+    tuning = b.autotune(reqs[I.KIND_U32], reps=2)
+    say(f"headline tuning {tuning}")
+    plans = [b.plan(reqs[k]) for k in kinds]
+    states = [O.seed_state(seeds[g], params[g].mexp) for g in range(G)]
+    for rep in range(2):
+        for p in plans:
+            p.launch()
+        torch.cuda.synchronize()
+        for k in kinds:
+            say(f"replay {rep} kind {k}")
+            host = outs[k].cpu().numpy().view(np.uint32)
+            with pool() as ex:
+                refs = list(ex.map(lambda g: O.generate(params[g], states[g], n, k), range(G)))
+            for g in range(G):
+                np.testing.assert_array_equal(host[g * n:(g + 1) * n], refs[g], err_msg=f"rep={rep} kind={k} gen={g}")
+    for g in range(G):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g])
+    for p in plans:
+        p.close()
+    b.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mexp,split", [(23209, 8192), (44497, 4096)])
+def test_large_states_full_size(M, mexp, split):
+    """256 generators x 2^24 uint32 (16 GiB) as the benchmark's tuned split
+    plan; eight generators' complete streams compared, and every final
+    state."""
+    import torch
+    params, n = I.large_states(mexp)
+    G = len(params)
+    seeds = I.state_seeds(G)
+    b = M.Batch(params, seeds)
+    b.set_split(split)
+    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+    plan = b.plan([(g, 0, n, out.data_ptr() + 4 * g * n) for g in range(G)])
+    say(f"p={mexp} split={split}")
+    plan.launch()
+    torch.cuda.synchronize()
+    sample = [0, 1, 37, 100, 128, 199, 254, 255]
+    states = {g: O.seed_state(seeds[g], mexp) for g in range(G)}
+    with pool() as ex:
+        refs = list(ex.map(lambda g: O.generate(params[g], states[g], n, 0), sample))
+    for g, ref in zip(sample, refs):
+        np.testing.assert_array_equal(device_words(out, g * n, n), ref, err_msg=f"p={mexp} gen={g}")
+    # the end state of every generator: advance the rest on the host
+    with pool() as ex:
+        list(ex.map(lambda g: O.advance(params[g], states[g], n), [g for g in range(G) if g not in sample]))
+    for g in range(G):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g], err_msg=f"p={mexp} state gen={g}")
+    plan.close()
+    b.close()
+    del out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_batched_uneven_full_size(M):
+    """4096 requests, exponents 2:1:1, lengths log-uniform in [2^10, 2^24],
+    mixed kinds, autotuned persistent plan: the 16 longest requests and 48
+    others compared in full."""
+    import torch
+    params, reqs = I.batched_uneven()
+    G = len(params)
+    seeds = I.state_seeds(G)
+    tot = sum(r.n for r in reqs)
+    b = M.Batch(params, seeds)
+    out = torch.empty(tot, dtype=torch.int32, device="cuda")
+    rq = [(r.gen, r.kind, r.n, out.data_ptr() + 4 * r.offset) for r in reqs]
+    tuning = b.autotune(rq, reps=1)
+    say(f"uneven tuning {tuning}")
+    plan = b.plan(rq)
+    plan.launch()
+    torch.cuda.synchronize()
+    longest = sorted(reqs, key=lambda r: r.n, reverse=True)[:16]
+    rng = I.SplitMix64(4096)
+    others = [reqs[rng.uniform_int(0, len(reqs) - 1)] for _ in range(48)]
+    sample = {r.gen: r for r in longest + others}.values()
+
+    def ref(r):
+        return O.generate(params[r.gen], O.seed_state(seeds[r.gen], params[r.gen].mexp), r.n, r.kind)
+
+    with pool() as ex:
+        refs = list(ex.map(ref, sample))
+    for r, want in zip(sample, refs):
+        np.testing.assert_array_equal(device_words(out, r.offset, r.n), want,
+                                      err_msg=f"gen={r.gen} mexp={params[r.gen].mexp} n={r.n} kind={r.kind}")
+    plan.close()
+    b.close()
+    del out
+    torch.cuda.empty_cache()
