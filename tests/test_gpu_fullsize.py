@@ -142,3 +142,57 @@ def test_batched_uneven_full_size(M):
     b.close()
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_native_server_full_size(M):
+    """65536 resident MTGP-11213 states behind the library's request loop with
+    the benchmark's arena and chunk, request sizes of the serving workload
+    (log-normal, median 2^16, clipped to [2^10, 2^26]), all submitted at once;
+    a quarter of the requests go to 64 busy generators so that FIFO order per
+    generator matters. Every request of the busy generators, the 12 largest
+    and 64 others are compared with the oracle's stream segments."""
+    import torch
+    from paper_1005_4973_amd import serve
+    G = 65536
+    params = I.serving_params(G)
+    seeds = I.state_seeds(G)
+    trace = I.serving_trace(3000, rate_per_s=1.0, num_gens=G, seed=5001)
+    trace = [(t, g % 64 if i % 4 == 0 else g, n, k) for i, (t, g, n, k) in enumerate(trace)]
+    b = M.Batch(params, seeds)
+    srv = serve.NativeServer(b, arena_bytes=8 << 30, chunk=1 << 18, depth=2)
+    busy = set(range(64))
+    largest = {rid for rid, _ in sorted(enumerate(trace), key=lambda e: e[1][2], reverse=True)[:12]}
+    rng = I.SplitMix64(777)
+    others = {rng.uniform_int(0, len(trace) - 1) for _ in range(64)}
+    wanted = {rid for rid, t in enumerate(trace) if t[1] in busy} | largest | others
+    got = {}
+
+    def keep(rid, view):
+        if rid in wanted:
+            got[rid] = view.cpu().numpy().view(np.uint32).copy()
+
+    say(f"server: {len(trace)} requests, {len(wanted)} checked")
+    st = srv.run(trace, realtime=False, on_complete=keep)
+    srv.close()
+    assert st.completed == len(trace) and set(got) == wanted
+    by_gen = {}
+    for rid, (_, g, n, k) in enumerate(trace):
+        by_gen.setdefault(g, []).append((rid, n, k))
+    gens = sorted({trace[rid][1] for rid in wanted})
+
+    def check(g):
+        s = O.seed_state(seeds[g], params[g].mexp)
+        for rid, n, k in by_gen[g]:
+            if rid in wanted:
+                np.testing.assert_array_equal(got[rid], O.generate(params[g], s, n, k), err_msg=f"rid={rid} gen={g}")
+            else:
+                O.advance(params[g], s, n)
+        return s
+
+    with pool() as ex:
+        finals = list(ex.map(check, gens))
+    for g, s in zip(gens, finals):   # the batch handle is used from this thread only
+        np.testing.assert_array_equal(b.get_state(g)[0], s, err_msg=f"state gen={g}")
+    b.close()
+    torch.cuda.empty_cache()
