@@ -261,8 +261,9 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecBa
 //       writes without a barrier or an LDS wait; the spl independent steps
 //       per lane hide the LDS latency instead.
 // Work comes from one item passed by value (grid of one), from item i for
-// unit i, or -- persistent form -- from a queue in `counters`, in the order
-// the host sorted the items (longest critical path first).
+// unit i, or -- persistent form -- item i for unit i first and then the
+// items past the grid from a queue in `counters`, in the order the host
+// sorted the items (longest critical path first).
 // LDS per unit: [0,16) recursion table, [16,32) output table, [32] queue
 // slot, then the window X of L words.
 // ---------------------------------------------------------------------------
@@ -324,18 +325,25 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             if (iter > 0 || w >= nitems)
                 break;
             it = items[w];
-        } else {                                // persistent: pop from the queue
+        } else {                                // persistent: own item first, then the queue
+            // unit w starts with item w, so the launch's first items need no
+            // atomic (a thousand units popping one counter at once delays the
+            // last of them measurably); the queue hands out the items after
+            // the first gridDim.x * units
+            const uint32_t units_total = gridDim.x * units;
             uint32_t q;
-            if (WAVE) {
+            if (iter == 0) {
+                q = blockIdx.x * units + unit;
+            } else if (WAVE) {
                 q = 0;
                 if (lane == 0)
                     q = atomicAdd(&counters[0], 1u);
-                q = __builtin_amdgcn_readfirstlane(q);
+                q = __builtin_amdgcn_readfirstlane(q) + units_total;
             } else {
                 if (lane == 0)
                     qslot[0] = atomicAdd(&counters[0], 1u);
                 __syncthreads();
-                q = __builtin_amdgcn_readfirstlane(qslot[0]);
+                q = __builtin_amdgcn_readfirstlane(qslot[0]) + units_total;
                 __syncthreads();
             }
             if (q >= nitems)
@@ -386,8 +394,13 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             __syncthreads();   // the next item overwrites the window and tables
     }
 
+    // Queue reset by the last unit to finish. Each unit's last pop returned
+    // its value (the loop tested it) before this increment is issued, so all
+    // pops are performed once the count reaches the total; no fence is
+    // needed (a device-scope fence here compiles to an L2 write-back and
+    // invalidate per unit, which slowed the launch's tail measurably). The
+    // outputs need none either: the end of the kernel makes them visible.
     if (items != nullptr && counters != nullptr && lane == 0) {
-        __threadfence();
         const uint32_t done = atomicAdd(&counters[1], 1u);
         if (done == gridDim.x * units - 1) {    // every pop has returned: reset for the next launch
             atomicExch(&counters[0], 0u);
