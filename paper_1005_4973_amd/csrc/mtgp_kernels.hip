@@ -261,9 +261,8 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecBa
 //       writes without a barrier or an LDS wait; the spl independent steps
 //       per lane hide the LDS latency instead.
 // Work comes from one item passed by value (grid of one), from item i for
-// unit i, or -- persistent form -- item i for unit i first and then the
-// items past the grid from a queue in `counters`, in the order the host
-// sorted the items (longest critical path first).
+// unit i, or -- persistent form -- from a queue in `counters`, in the order
+// the host sorted the items (longest critical path first).
 // LDS per unit: [0,16) recursion table, [16,32) output table, [32] queue
 // slot, then the window X of L words.
 // ---------------------------------------------------------------------------
@@ -325,25 +324,21 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             if (iter > 0 || w >= nitems)
                 break;
             it = items[w];
-        } else {                                // persistent: own item first, then the queue
-            // unit w starts with item w, so the launch's first items need no
-            // atomic (a thousand units popping one counter at once delays the
-            // last of them measurably); the queue hands out the items after
-            // the first gridDim.x * units
-            const uint32_t units_total = gridDim.x * units;
+        } else {                                // persistent: pop from the queue
+            // (units that start late -- a grid larger than what fits at once
+            // -- then take the next item in order, which keeps the longest-
+            // first order; assigning item w to unit w up front did not)
             uint32_t q;
-            if (iter == 0) {
-                q = blockIdx.x * units + unit;
-            } else if (WAVE) {
+            if (WAVE) {
                 q = 0;
                 if (lane == 0)
                     q = atomicAdd(&counters[0], 1u);
-                q = __builtin_amdgcn_readfirstlane(q) + units_total;
+                q = __builtin_amdgcn_readfirstlane(q);
             } else {
                 if (lane == 0)
                     qslot[0] = atomicAdd(&counters[0], 1u);
                 __syncthreads();
-                q = __builtin_amdgcn_readfirstlane(qslot[0]) + units_total;
+                q = __builtin_amdgcn_readfirstlane(qslot[0]);
                 __syncthreads();
             }
             if (q >= nitems)
