@@ -55,6 +55,16 @@ def test_host_only_calls():
     assert L.mtgp_plan_launch_phase(None, mtgp.PHASE_GENERATE, None) == mtgp.MTGP_EINVAL
     assert L.mtgp_batch_autotune(None, None, 1, None, 3, None) == mtgp.MTGP_EINVAL
     assert L.mtgp_batch_set_split(None, 8) == mtgp.MTGP_EINVAL
+    # the request loop: bad creation arguments give NULL, NULL handles EINVAL
+    assert L.mtgp_server_create(None, None, 1 << 20, 1 << 10, 2, None) is None
+    assert L.mtgp_server_submit(None, None, 1) == mtgp.MTGP_EINVAL
+    assert L.mtgp_server_poll(None, None, 0, None) == mtgp.MTGP_EINVAL
+    assert L.mtgp_server_release(None, None, 1) == mtgp.MTGP_EINVAL
+    assert L.mtgp_server_pending(None, None, None, None) == mtgp.MTGP_EINVAL
+    L.mtgp_server_destroy(None)
+    # host-only analyses reject NULL outputs
+    assert L.mtgp_search_params(11213, 1, 1, 10, 1, None, None) == mtgp.MTGP_EINVAL
+    assert L.mtgp_equidistribution(None, 1, 32, None, None) == mtgp.MTGP_EINVAL
 
 
 def test_create_rejects_bad_parameters_before_touching_the_device():
