@@ -753,9 +753,10 @@ int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem>
         if (!replaced[i])
             out.push_back(items[i]);
     items.swap(out);
-    // the jump kernel is launched once per lane width
+    // the jump kernel is launched once per lane width and word-group count
     std::stable_sort(jumps.begin(), jumps.end(), [](const JumpItem &x, const JumpItem &y) {
-        return jump_shape(x.N).R < jump_shape(y.N).R;
+        const JumpShape a = jump_shape(x.N), b = jump_shape(y.N);
+        return a.R != b.R ? a.R < b.R : a.G < b.G;
     });
     // upload the polynomials (only their regions are meaningful)
     for (size_t i = 0; i < ok.size(); i++) {
@@ -1520,7 +1521,8 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     // launch shapes at the best split limit
     const uint32_t split = best_of().split;
     const int shapes[][3] = {{kModeGroup, 256, 1}, {kModeGroup, 256, 2}, {kModeGroup, 512, 1},
-                             {kModeGroup, 128, 4}, {kModeWave, 256, 8}};
+                             {kModeGroup, 512, 2}, {kModeGroup, 1024, 1}, {kModeGroup, 128, 4},
+                             {kModeWave, 256, 8}};
     for (const auto &sh : shapes) {
         if (!device_ok)
             break;

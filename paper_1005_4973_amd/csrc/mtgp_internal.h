@@ -58,8 +58,9 @@ static_assert(sizeof(JumpItem) == 32, "JumpItem layout");
 
 // Geometry of the jump kernel for a state of N words: a lane owns R
 // consecutive words (6 <= R <= 16), a wavefront covers 64 R words, G
-// wavefronts cover the N words and the P = 4 / G wavefronts of each word group
-// split the bits of h. raw is staged through LDS CI iterations of 4R bits at a
+// wavefronts cover the N words and P wavefronts of each word group split the
+// bits of h (P = 4 / G here, the least a launch uses; launch_jumps may double
+// it). raw is staged through LDS CI iterations of 4R bits at a
 // time. Per bit of h a wavefront does about R / 2 XORs and one cross-lane move
 // per lane, so R is chosen for the least G (R + 2), then for all four
 // wavefronts busy, then the smaller R.
@@ -160,9 +161,9 @@ hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkIt
                            uint32_t nitems, uint32_t *counters, const WorkItem &single,
                            const LaunchShape &shape, hipStream_t stream);
 
-// One workgroup of 256 lanes per jump item (geometry jump_shape(N)); d_items
-// on the device, h_items the same items on the host, grouped by lane width
-// (one launch per run of equal widths).
+// One workgroup of 64 G P lanes per jump item (geometry jump_shape(N), P
+// chosen per launch); d_items on the device, h_items the same items on the
+// host, grouped by lane width and word groups (one launch per run).
 hipError_t launch_jumps(const JumpItem *d_items, const JumpItem *h_items, uint32_t nitems, hipStream_t stream);
 
 // Allow every generation kernel to use up to `bytes` of dynamic LDS.

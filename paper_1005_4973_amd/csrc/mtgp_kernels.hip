@@ -426,7 +426,7 @@ hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkIt
 // S, F S, F^2 S, ... selected by the coefficients of h = x^J mod psi (psi an
 // annihilating polynomial of S), i.e. out[w] = XOR_{i: h_i = 1} raw[i + w].
 //
-// One workgroup of 4 wavefronts per jump. Lane l of wavefront g owns the R
+// One workgroup of G P wavefronts per jump. Lane l of wavefront g owns the R
 // consecutive words w0 .. w0+R-1 (w0 = 64 R g + R l) and slides a 2R-word
 // window (lo, hi) = raw[i + w0 .. i + w0 + 2R) over the bits of h: per block
 // of R bits it XORs, for each set bit t (a uniform scalar test), the window
@@ -439,7 +439,6 @@ hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkIt
 // raw and read one iteration ahead.
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kJumpLanes = 256;
 constexpr int kDppWaveShl1 = 0x130;   // DPP control: lane k reads lane k + 1; lane 63 keeps `old`
 
 // One block: R bits hb of h over the window (lo, hi); then nx = the next hi,
@@ -476,7 +475,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 }
 
 template <uint32_t R>
-__global__ __launch_bounds__(256) void mtgp_jump_kernel(const JumpItem *__restrict__ items)
+__global__ __launch_bounds__(1024) void mtgp_jump_kernel(const JumpItem *__restrict__ items)
 {
     extern __shared__ uint32_t Xs[];
     const JumpItem it = items[blockIdx.x];
@@ -484,7 +483,8 @@ __global__ __launch_bounds__(256) void mtgp_jump_kernel(const JumpItem *__restri
     constexpr uint32_t STEP = 4 * R;        // bits (and raw words) per iteration
     const JumpShape sh = jump_shape(it.N);  // sh.R == R
     const uint32_t N = it.N, D = it.D;
-    const uint32_t G = sh.G, P = sh.P, CI = sh.CI;
+    // P wavefronts per word group: the launch sizes the workgroup to G * P wavefronts
+    const uint32_t G = sh.G, P = (blockDim.x >> 6) / sh.G, CI = sh.CI;
     const uint32_t raw_words = 4 * R * CI + G * W + 6 * R;
     uint64_t *Ps = reinterpret_cast<uint64_t *>(Xs + (raw_words + 1) / 2 * 2);
     const uint32_t *raw = reinterpret_cast<const uint32_t *>(it.raw);
@@ -508,9 +508,9 @@ __global__ __launch_bounds__(256) void mtgp_jump_kernel(const JumpItem *__restri
         const uint32_t ci = iters - s0 < CI ? iters - s0 : CI;
         const uint32_t i0 = s0 * STEP;
         const uint32_t cnt = D - i0 < ci * STEP ? D - i0 : ci * STEP;
-        for (uint32_t k = threadIdx.x; k < cnt + N - 1; k += kJumpLanes)
+        for (uint32_t k = threadIdx.x; k < cnt + N - 1; k += blockDim.x)
             Xs[k] = raw[i0 + k];
-        for (uint32_t k = threadIdx.x; k < ci; k += kJumpLanes)
+        for (uint32_t k = threadIdx.x; k < ci; k += blockDim.x)
             Ps[k] = poly[s0 + k];
         __syncthreads();
         if (active) {
@@ -566,36 +566,53 @@ __global__ __launch_bounds__(256) void mtgp_jump_kernel(const JumpItem *__restri
 }
 
 template <uint32_t R>
-hipError_t launch_jump_run(const JumpItem *items, uint32_t n, size_t lds, hipStream_t stream)
+hipError_t launch_jump_run(const JumpItem *items, uint32_t n, uint32_t threads, size_t lds, hipStream_t stream)
 {
-    hipLaunchKernelGGL(mtgp_jump_kernel<R>, dim3(n), dim3(kJumpLanes), lds, stream, items);
+    hipLaunchKernelGGL(mtgp_jump_kernel<R>, dim3(n), dim3(threads), lds, stream, items);
     return hipGetLastError();
 }
 
 template <uint32_t R>
-hipError_t launch_jump_width(uint32_t width, const JumpItem *items, uint32_t n, size_t lds, hipStream_t stream)
+hipError_t launch_jump_width(uint32_t width, const JumpItem *items, uint32_t n, uint32_t threads, size_t lds,
+                             hipStream_t stream)
 {
     if constexpr (R > kJumpMaxR) {
         return hipErrorInvalidValue;
     } else {
-        return width == R ? launch_jump_run<R>(items, n, lds, stream)
-                          : launch_jump_width<R + 1>(width, items, n, lds, stream);
+        return width == R ? launch_jump_run<R>(items, n, threads, lds, stream)
+                          : launch_jump_width<R + 1>(width, items, n, threads, lds, stream);
     }
 }
 
 hipError_t launch_jumps(const JumpItem *d_items, const JumpItem *h_items, uint32_t nitems, hipStream_t stream)
 {
-    // one launch per run of items with the same lane width
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    // one launch per run of items with the same lane width and word groups
     uint32_t k = 0;
     while (k < nitems) {
-        const uint32_t R = jump_shape(h_items[k].N).R;
+        const JumpShape s = jump_shape(h_items[k].N);
         uint32_t e = k;
-        uint32_t words = 0;
-        while (e < nitems && jump_shape(h_items[e].N).R == R) {
-            words = jump_lds_words(h_items[e].N) > words ? jump_lds_words(h_items[e].N) : words;
+        while (e < nitems && jump_shape(h_items[e].N).R == s.R && jump_shape(h_items[e].N).G == s.G)
             e++;
+        // Each jump is a sequential pass over the bits of h split among P
+        // wavefronts per word group; with few jumps per CU that pass is the
+        // launch's latency, so P doubles (up to 16 wavefronts a workgroup)
+        // until about 16 wavefronts per CU are busy.
+        uint32_t P = s.P;
+        while (s.G * P * 2 <= 16 && (uint64_t)(e - k) * s.G * P < 16ull * (uint64_t)cus)
+            P *= 2;
+        uint32_t words = 0;
+        for (uint32_t i = k; i < e; i++) {
+            const uint32_t own = jump_lds_words(h_items[i].N);
+            const uint32_t sums = (P - 1) * s.G * 64 * s.R;   // partial sums of the extra wavefronts
+            words = own > words ? own : words;
+            words = sums > words ? sums : words;
         }
-        const hipError_t err = launch_jump_width<kJumpMinR>(R, d_items + k, e - k, (size_t)words * 4u, stream);
+        const hipError_t err =
+            launch_jump_width<kJumpMinR>(s.R, d_items + k, e - k, 64 * s.G * P, (size_t)words * 4u, stream);
         if (err != hipSuccess)
             return err;
         k = e;
