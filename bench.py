@@ -412,7 +412,8 @@ def main():
     log(f"headline: {head['value']} G numbers/s")
 
     res = {
-        "metric": "G numbers/s (uint32 and float32 outputs) and % of HBM write roofline",
+        # the workload's metric; uint32 and float32 outputs count alike (one 32-bit word each)
+        "metric": "G uint32/s & % HBM write roofline, batched vs plain; p99 request latency",
         "value": head["value"],
         "unit": "G numbers/s",
         "n_gpus": 1,
