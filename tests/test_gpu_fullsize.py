@@ -1,8 +1,9 @@
 """Parity at the workloads' full sizes, in the configurations the benchmark
-times: autotuned jump-ahead plans for the 128 x 2^22 headline (every output
-of every kind), the 256 x 2^24 large-state batches and the 4096-request
-uneven batch (complete streams of sampled generators, the longest among
-them). The oracle runs on host threads (its C calls release the GIL).
+times: autotuned jump-ahead plans for the 128 x 2^22 headline, the 256 x
+2^24 large-state batches and the 4096-request uneven batch (every output of
+every generator, copied back in chunks), and the native request loop over
+65536 states (sampled requests). The oracle runs on host threads (its C
+calls release the GIL).
 """
 import os
 from concurrent.futures import ThreadPoolExecutor
@@ -73,12 +74,12 @@ def test_headline_tuned_plans_full_size(M):
     b.close()
 
 
-@pytest.mark.timeout(600)
-@pytest.mark.parametrize("mexp,split", [(23209, 8192), (44497, 4096)])
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("mexp,split", [(23209, 8192), (44497, 8192)])
 def test_large_states_full_size(M, mexp, split):
     """256 generators x 2^24 uint32 (16 GiB) as the benchmark's tuned split
-    plan; eight generators' complete streams compared, and every final
-    state."""
+    plan; every generator's complete stream compared (copied back 16
+    generators at a time), and every final state."""
     import torch
     params, n = I.large_states(mexp)
     G = len(params)
@@ -90,15 +91,16 @@ def test_large_states_full_size(M, mexp, split):
     say(f"p={mexp} split={split}")
     plan.launch()
     torch.cuda.synchronize()
-    sample = [0, 1, 37, 100, 128, 199, 254, 255]
     states = {g: O.seed_state(seeds[g], mexp) for g in range(G)}
+    chunk = 16
     with pool() as ex:
-        refs = list(ex.map(lambda g: O.generate(params[g], states[g], n, 0), sample))
-    for g, ref in zip(sample, refs):
-        np.testing.assert_array_equal(device_words(out, g * n, n), ref, err_msg=f"p={mexp} gen={g}")
-    # the end state of every generator: advance the rest on the host
-    with pool() as ex:
-        list(ex.map(lambda g: O.advance(params[g], states[g], n), [g for g in range(G) if g not in sample]))
+        for g0 in range(0, G, chunk):
+            gens = range(g0, min(G, g0 + chunk))
+            host = device_words(out, g0 * n, len(gens) * n)
+            refs = list(ex.map(lambda g: O.generate(params[g], states[g], n, 0), gens))
+            for g, ref in zip(gens, refs):
+                np.testing.assert_array_equal(host[(g - g0) * n:(g - g0 + 1) * n], ref, err_msg=f"p={mexp} gen={g}")
+    say(f"p={mexp}: all {G} streams equal")
     for g in range(G):
         np.testing.assert_array_equal(b.get_state(g)[0], states[g], err_msg=f"p={mexp} state gen={g}")
     plan.close()
@@ -107,11 +109,11 @@ def test_large_states_full_size(M, mexp, split):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_batched_uneven_full_size(M):
     """4096 requests, exponents 2:1:1, lengths log-uniform in [2^10, 2^24],
-    mixed kinds, autotuned persistent plan: the 16 longest requests and 48
-    others compared in full."""
+    mixed kinds, autotuned persistent plan: every request's outputs compared
+    (copied back about 1 GiB at a time), and every final state."""
     import torch
     params, reqs = I.batched_uneven()
     G = len(params)
@@ -125,19 +127,28 @@ def test_batched_uneven_full_size(M):
     plan = b.plan(rq)
     plan.launch()
     torch.cuda.synchronize()
-    longest = sorted(reqs, key=lambda r: r.n, reverse=True)[:16]
-    rng = I.SplitMix64(4096)
-    others = [reqs[rng.uniform_int(0, len(reqs) - 1)] for _ in range(48)]
-    sample = {r.gen: r for r in longest + others}.values()
-
-    def ref(r):
-        return O.generate(params[r.gen], O.seed_state(seeds[r.gen], params[r.gen].mexp), r.n, r.kind)
-
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(G)}
+    # requests are packed in order: compare them in groups of about 2^28 outputs
+    groups, cur, size = [], [], 0
+    for r in reqs:
+        cur.append(r)
+        size += r.n
+        if size >= 1 << 28:
+            groups.append(cur)
+            cur, size = [], 0
+    if cur:
+        groups.append(cur)
     with pool() as ex:
-        refs = list(ex.map(ref, sample))
-    for r, want in zip(sample, refs):
-        np.testing.assert_array_equal(device_words(out, r.offset, r.n), want,
-                                      err_msg=f"gen={r.gen} mexp={params[r.gen].mexp} n={r.n} kind={r.kind}")
+        for grp in groups:
+            base = grp[0].offset
+            host = device_words(out, base, grp[-1].offset + grp[-1].n - base)
+            refs = list(ex.map(lambda r: O.generate(params[r.gen], states[r.gen], r.n, r.kind), grp))
+            for r, want in zip(grp, refs):
+                np.testing.assert_array_equal(host[r.offset - base:r.offset - base + r.n], want,
+                                              err_msg=f"gen={r.gen} mexp={params[r.gen].mexp} n={r.n} kind={r.kind}")
+    say(f"uneven: all {len(reqs)} requests equal")
+    for g in range(G):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g], err_msg=f"state gen={g}")
     plan.close()
     b.close()
     del out
