@@ -18,17 +18,10 @@
 // overwrites before reading it. Hence the window needs L >= 2N + lanes*spl
 // (source and destination of the compaction copy are then disjoint too).
 // Loads of a round are issued first, then the tempering lookups, then the
-// recursion's VALU work and the writes; the lookups return while the VALU
-// work runs, so a round's chain is its loads, that work, its writes and the
-// barrier.
-//
-// The recursion table is F2-linear (the library rejects any other table):
-// rec[u & 0xf] is the XOR of rec[1 << b] over the set bits b < 4 of u. The
-// kernel evaluates it that way -- four sign-extended bit masks and four
-// 3-input bit operations against the basis words held in scalar registers --
-// so the dependent chain from the round's loads to its writes has no table
-// lookup in it. Only the tempering lookup, which the next round does not
-// wait for, goes through LDS.
+// recursion's VALU work, its table lookup and the writes; the tempering
+// lookups return while that work runs, so a round's chain is its loads, the
+// recursion, one lookup, its writes and the barrier. Both 16-word tables
+// (recursion and output) sit in LDS ahead of the window.
 //
 // Step k of a round is done by lane k mod T in pass k / T (T = workgroup
 // size), so LDS reads and writes are unit-stride across a wavefront and the
@@ -36,7 +29,7 @@
 //
 // Per step (section 3.6 and 3.7):
 //   t = x_{i+1} ^ (x_i & mask);  t ^= t << sh1;  u = t ^ (x_{i+M} >> sh2)
-//   x_{i+N} = u ^ rec[u & 0xf]        (rec evaluated from its four basis words)
+//   x_{i+N} = u ^ rec[u & 0xf]
 //   s = x_{i+M-1} ^ (x_{i+M-1} >> 16);  s ^= s >> 8
 //   uint32:      o = x_{i+N} ^ tmp[s & 0xf]
 //   float [1,2): o = (x_{i+N} >> 9) ^ flt[s & 0xf]       (section 6, eq. (C))
@@ -50,7 +43,8 @@
 
 namespace mtgp_impl {
 
-// LDS layout: [16,32) output table, [32] queue slot, window X from word 64 on.
+// LDS layout: [0,16) recursion table, [16,32) output table, [32] queue slot,
+// window X from word 64 on.
 constexpr uint32_t kTableWords = 64;
 
 // Outputs are written with buffer stores (see out_window): unlike flat
@@ -127,32 +121,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_window(gu32 *p, uint32_t c
 }
 
 // One round: SPL step slots per lane, slot c of lane `lane` is step
-// k = lane + c*T of the round (T lanes). Xb points at x_{i0}.
-// The recursion table's basis words rec[1], rec[2], rec[4], rec[8].
-struct RecBasis {
-    uint32_t r0, r1, r2, r3;
-};
-
-// x ^ (all-ones if bit b of u is set, else 0) & r, as one 3-input bit op
-// (truth table 0x78 = a ^ (b & c) over the operand order x, mask, r).
-template <int B>
-__device__ __forceinline__ uint32_t xor_if_bit(uint32_t x, uint32_t u, uint32_t r)
-{
-    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)u, B, 1);
-    return __builtin_amdgcn_bitop3_b32(x, m, r, (uint8_t)0x78);
-}
-
-// u ^ rec[u & 0xf] for an F2-linear rec given by its basis.
-__device__ __forceinline__ uint32_t add_rec(uint32_t u, const RecBasis &rb)
-{
-    uint32_t x = xor_if_bit<0>(u, u, rb.r0);
-    x = xor_if_bit<1>(x, u, rb.r1);
-    x = xor_if_bit<2>(x, u, rb.r2);
-    return xor_if_bit<3>(x, u, rb.r3);
-}
-
+// k = lane + c*T of the round (T lanes). Xb points at x_{i0}; rtb and otb
+// are the 16-word recursion and output tables in LDS. Both lookups are LDS
+// reads (16 distinct words in 16 banks: no conflicts). Evaluating rec from its
+// four F2 basis words in registers instead keeps the lookup off the round's
+// dependency chain but costs 8 vector instructions per step against 3; the
+// lookup form measured about 6 % faster.
 template <int KIND, int SPL>
-__device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const RecBasis &rb,
+__device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const uint32_t *__restrict__ rtb,
                                             const uint32_t *__restrict__ otb, uint32_t N, uint32_t M,
                                             uint32_t sh1, uint32_t sh2, uint32_t mask, uint32_t lane,
                                             uint32_t T, uint32_t cnt, gu32 *__restrict__ ob)
@@ -178,7 +154,7 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const Rec
         const uint32_t a = xi1[c] ^ (xi[c] & mask);
         // u = a ^ (a << sh1) ^ (x_{i+M} >> sh2) as one 3-input XOR (truth table 0x96)
         const uint32_t u = __builtin_amdgcn_bitop3_b32(a << sh1, xm[c] >> sh2, a, (uint8_t)0x96);
-        x[c] = add_rec(u, rb);
+        x[c] = u ^ rtb[u & 0xfu];
         Xb[N + lane + c * T] = x[c];
     }
     const __amdgpu_buffer_rsrc_t rsrc = out_window(ob, cnt);
@@ -199,7 +175,7 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const Rec
 // form every wavefront repeats it. WAVE: one wavefront, no barriers (LDS
 // operations of a wavefront complete in order).
 template <int KIND, int SPL, bool WAVE>
-__device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecBasis &rec,
+__device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const uint32_t *__restrict__ rtb,
                                            const uint32_t *__restrict__ otb, uint32_t N, uint32_t M,
                                            uint32_t sh1, uint32_t sh2, uint32_t mask, uint32_t W,
                                            uint32_t L, uint64_t n, gu32 *__restrict__ out,
@@ -223,7 +199,7 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecBa
         const uint32_t room = (L - N - span - base) / W + 1;
         const uint32_t k = full < room ? (uint32_t)full : room;
         for (uint32_t j = 0; j < k; ++j) {
-            round_steps<KIND, SPL>(X + base, rec, otb, N, M, sh1, sh2, mask, lane, T, W, ob);
+            round_steps<KIND, SPL>(X + base, rtb, otb, N, M, sh1, sh2, mask, lane, T, W, ob);
             if (!WAVE)
                 __syncthreads();
             base += W;
@@ -239,7 +215,7 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecBa
                 __syncthreads();
             base = 0;
         }
-        round_steps<KIND, SPL>(X + base, rec, otb, N, M, sh1, sh2, mask, lane, T, rem, ob);
+        round_steps<KIND, SPL>(X + base, rtb, otb, N, M, sh1, sh2, mask, lane, T, rem, ob);
         if (!WAVE)
             __syncthreads();
         base += rem;
@@ -268,12 +244,12 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecBa
 // ---------------------------------------------------------------------------
 
 template <int KIND, bool WAVE>
-__device__ __forceinline__ void run_item(uint32_t spl, uint32_t *X, const RecBasis &rec, const uint32_t *otb,
+__device__ __forceinline__ void run_item(uint32_t spl, uint32_t *X, const uint32_t *rtb, const uint32_t *otb,
                                          const GenRecord &g, uint32_t W, uint32_t L, uint64_t n, gu32 *out,
                                          uint32_t *state, uint32_t lane, uint32_t T)
 {
 #define MTGP_RUN(S) \
-    run_stream<KIND, S, WAVE>(X, rec, otb, g.N, g.M, g.sh1, g.sh2, g.mask, W, L, n, out, state, lane, T)
+    run_stream<KIND, S, WAVE>(X, rtb, otb, g.N, g.M, g.sh1, g.sh2, g.mask, W, L, n, out, state, lane, T)
     if (WAVE) {
         switch (spl) {
         case 1: MTGP_RUN(1); break;
@@ -309,6 +285,7 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
     const uint32_t unit = WAVE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0u;
     const uint32_t units = WAVE ? (blockDim.x >> 6) : 1u;
     uint32_t *unit_lds = smem + unit * (kTableWords + L);
+    uint32_t *rtb = unit_lds;
     uint32_t *otb = unit_lds + 16;
     uint32_t *qslot = unit_lds + 32;
     uint32_t *X = unit_lds + kTableWords;
@@ -362,9 +339,10 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
 
         for (uint32_t k = lane; k < N; k += T)
             X[k] = from[k];
-        if (lane < 16)
+        if (lane < 16) {
+            rtb[lane] = g.rec[lane];
             otb[lane] = kind == 0 ? g.tmp[lane] : g.flt[lane];
-        const RecBasis rb = {g.rec[1], g.rec[2], g.rec[4], g.rec[8]};
+        }
         if (!WAVE)
             __syncthreads();
 
@@ -376,15 +354,15 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             out += N;
         }
         if (kind == kKindU32)
-            run_item<kKindU32, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindU32, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindF12)
-            run_item<kKindF12, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindF12, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindF01)
-            run_item<kKindF01, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindF01, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindNormal)
-            run_item<kKindNormal, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindNormal, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
         else
-            run_item<kKindRaw, WAVE>(spl, X, rb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindRaw, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
         if (!WAVE)
             __syncthreads();   // the next item overwrites the window and tables
     }
