@@ -227,8 +227,9 @@ void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's la
  * plan launches on `stream` for each candidate configuration -- the automatic
  * launch shape with no split and with split limits halving from the longest
  * request's round count down to 128 rounds, then, at the best split limit,
- * workgroup forms of 128/256/512 lanes with 1-4 steps per lane and the
- * wavefront form -- and keeps the fastest (a later candidate must be at least
+ * workgroup forms of 128/256/512/1024 lanes with 1-4 steps per lane and the
+ * wavefront form, then the best of these with the other recursion-table
+ * form (MTGP_MODE_REC_BASIS) -- and keeps the fastest (a later candidate must be at least
  * 2 % faster than the one it replaces) as the batch's launch shape
  * (mtgp_batch_set_launch) and split limit (mtgp_batch_set_split). Outputs are
  * identical under every configuration; the generators' states and counters
@@ -239,7 +240,7 @@ void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's la
  * previous settings are then kept).
  */
 typedef struct {
-    int mode, threads, spl;   /* chosen shape; mode -1: the automatic shape */
+    int mode, threads, spl;   /* chosen shape; mode -1: the automatic shape (mode may carry MTGP_MODE_REC_BASIS) */
     uint32_t split_rounds;    /* chosen split limit (0: no split) */
     float ms;                 /* its mean plan launch time */
     uint32_t trials;          /* configurations timed */
@@ -253,6 +254,11 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
  *           rounds; steps per lane per round up to `spl` (1, 2 or 4).
  *   mode 1: one wavefront per generator, `threads`/64 wavefronts per
  *           workgroup, no barriers; spl up to 1, 2, 4, 6, 8, 12 or 16.
+ *   mode | MTGP_MODE_REC_BASIS: the recursion table rec[u & 0xf] is evaluated
+ *           from its four F2 basis words in registers instead of read from
+ *           LDS: more vector instructions per step, but no lookup on the
+ *           chain of a round (faster where one generator's chain of rounds
+ *           sets the launch time, slower where many generators share a CU).
  * Each generator uses the largest supported s <= spl with lanes*s <= N - M
  * (lanes = threads in mode 0, 64 in mode 1), so a round computes
  * W = min(N - M, lanes*s) steps (section 3.2). lds_words is the LDS window per
@@ -262,6 +268,7 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
  * shape; a batch call whose requests do not fit the shape fails with
  * MTGP_EINVAL.
  * ------------------------------------------------------------------------- */
+#define MTGP_MODE_REC_BASIS 4
 int mtgp_batch_set_launch(mtgp_batch_t *b, int mode, int threads, int spl, int lds_words, int grid);
 int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words);
 

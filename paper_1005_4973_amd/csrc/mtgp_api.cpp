@@ -6,6 +6,8 @@
 #include "mtgp_f2.h"
 #include "mtgp_internal.h"
 
+static_assert(mtgp_impl::kModeRecBasis == MTGP_MODE_REC_BASIS, "launch mode flag");
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -300,6 +302,7 @@ int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, Launc
         b->override_shape.grid == 0) {
         // workgroup form with automatic window and grid: placed like the default
         s = batch_default_shape(b, items, b->override_shape.threads, b->override_shape.spl);
+        s.rec_basis = b->override_shape.rec_basis;
     } else if (b->have_override) {
         s = b->override_shape;
         if (s.lds_words == 0) {
@@ -1101,6 +1104,8 @@ int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words)
         return MTGP_OK;
     }
     LaunchShape s;
+    s.rec_basis = (mode & kModeRecBasis) ? 1 : 0;
+    mode &= ~kModeRecBasis;
     s.mode = mode;
     s.threads = mode == kModeGroup ? threads : 64;
     s.spl = spl;
@@ -1271,7 +1276,8 @@ int mtgp_batch_set_launch(mtgp_batch_t *b, int mode, int threads, int spl, int l
         return MTGP_OK;
     }
     LaunchShape s;
-    s.mode = mode;
+    s.rec_basis = (mode & kModeRecBasis) ? 1 : 0;
+    s.mode = mode & ~kModeRecBasis;
     s.threads = threads;
     s.spl = spl;
     s.lds_words = lds_words > 0 ? lds_words : 1;
@@ -1540,6 +1546,23 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
         trial(c);
         tried.push_back(c);
     }
+    // the best so far with the other recursion-table form (the automatic
+    // shape is the 256-lane workgroup form with up to 4 steps per lane)
+    if (device_ok) {
+        Cand c = best_of();
+        if (c.automatic) {
+            c.automatic = false;
+            c.shape = LaunchShape{};
+            c.shape.mode = kModeGroup;
+            c.shape.threads = 256;
+            c.shape.spl = 4;
+            c.shape.lds_words = 0;
+            c.shape.grid = 0;
+        }
+        c.shape.rec_basis = 1 - c.shape.rec_basis;
+        trial(c);
+        tried.push_back(c);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(d_save);
@@ -1554,7 +1577,7 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     b->override_shape = win.shape;
     b->split_rounds = win.split;
     if (best) {
-        best->mode = win.automatic ? -1 : win.shape.mode;
+        best->mode = win.automatic ? -1 : (win.shape.mode | (win.shape.rec_basis ? kModeRecBasis : 0));
         best->threads = win.automatic ? 0 : win.shape.threads;
         best->spl = win.automatic ? 0 : win.shape.spl;
         best->split_rounds = win.split;

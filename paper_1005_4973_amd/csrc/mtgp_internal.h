@@ -111,6 +111,7 @@ static_assert(sizeof(WorkItem) == 32, "WorkItem layout");
 // Launch shape of the generation kernels.
 constexpr int kModeGroup = 0;   // one workgroup per generator, a barrier per round
 constexpr int kModeWave = 1;    // one wavefront per generator, no barriers
+constexpr int kModeRecBasis = 4; // flag in the public mode value: LaunchShape::rec_basis
 
 struct LaunchShape {
     int mode;        // kModeGroup or kModeWave
@@ -119,6 +120,7 @@ struct LaunchShape {
                      // (group: 1, 2, 4; wave: 1, 2, 4, 6, 8, 12, 16)
     int lds_words;   // LDS window length L in words per generator (>= 2N + lanes*spl of every item)
     int grid;        // workgroups
+    int rec_basis = 0;  // 1: recursion table from its F2 basis in registers, 0: LDS lookup
 };
 
 inline uint32_t shape_lanes(const LaunchShape &s) { return s.mode == kModeGroup ? (uint32_t)s.threads : 64u; }

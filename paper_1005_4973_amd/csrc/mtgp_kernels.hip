@@ -120,15 +120,50 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_window(gu32 *p, uint32_t c
     return __builtin_amdgcn_make_buffer_rsrc(static_cast<void *>(q), 0, (int)bytes, kBufferWord3);
 }
 
+// The recursion table rec[u & 0xf], evaluated one of two ways:
+//   lookup (BASIS = false): a read of the 16-word table in LDS (3 vector
+//       instructions per step, but the read sits on the round's chain);
+//   basis  (BASIS = true): the table is F2-linear (the library rejects any
+//       other), so rec[u & 0xf] is the XOR of rec[1 << b] over the set bits
+//       b < 4 of u -- four sign-extended bit masks and four 3-input bit
+//       operations against basis words in scalar registers (8 instructions,
+//       no lookup on the chain).
+// Throughput-bound launches (many generators per CU) run faster with the
+// lookup, launches whose time is one generator's chain of rounds with the
+// basis form; the launch shape chooses.
+struct RecTable {
+    const uint32_t *lds;          // rec[0..16) in LDS
+    uint32_t b0, b1, b2, b3;      // rec[1], rec[2], rec[4], rec[8]
+};
+
+// x ^ (all-ones if bit b of u is set, else 0) & r, as one 3-input bit op
+// (truth table 0x78 = a ^ (b & c) over the operand order x, mask, r).
+template <int B>
+__device__ __forceinline__ uint32_t xor_if_bit(uint32_t x, uint32_t u, uint32_t r)
+{
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)u, B, 1);
+    return __builtin_amdgcn_bitop3_b32(x, m, r, (uint8_t)0x78);
+}
+
+// u ^ rec[u & 0xf]
+template <bool BASIS>
+__device__ __forceinline__ uint32_t add_rec(uint32_t u, const RecTable &rt)
+{
+    if constexpr (BASIS) {
+        uint32_t x = xor_if_bit<0>(u, u, rt.b0);
+        x = xor_if_bit<1>(x, u, rt.b1);
+        x = xor_if_bit<2>(x, u, rt.b2);
+        return xor_if_bit<3>(x, u, rt.b3);
+    } else {
+        return u ^ rt.lds[u & 0xfu];
+    }
+}
+
 // One round: SPL step slots per lane, slot c of lane `lane` is step
-// k = lane + c*T of the round (T lanes). Xb points at x_{i0}; rtb and otb
-// are the 16-word recursion and output tables in LDS. Both lookups are LDS
-// reads (16 distinct words in 16 banks: no conflicts). Evaluating rec from its
-// four F2 basis words in registers instead keeps the lookup off the round's
-// dependency chain but costs 8 vector instructions per step against 3; the
-// lookup form measured about 6 % faster.
-template <int KIND, int SPL>
-__device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const uint32_t *__restrict__ rtb,
+// k = lane + c*T of the round (T lanes). Xb points at x_{i0}; otb is the
+// 16-word output table in LDS (16 distinct words in 16 banks: no conflicts).
+template <int KIND, int SPL, bool BASIS>
+__device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const RecTable &rt,
                                             const uint32_t *__restrict__ otb, uint32_t N, uint32_t M,
                                             uint32_t sh1, uint32_t sh2, uint32_t mask, uint32_t lane,
                                             uint32_t T, uint32_t cnt, gu32 *__restrict__ ob)
@@ -154,7 +189,7 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const uin
         const uint32_t a = xi1[c] ^ (xi[c] & mask);
         // u = a ^ (a << sh1) ^ (x_{i+M} >> sh2) as one 3-input XOR (truth table 0x96)
         const uint32_t u = __builtin_amdgcn_bitop3_b32(a << sh1, xm[c] >> sh2, a, (uint8_t)0x96);
-        x[c] = u ^ rtb[u & 0xfu];
+        x[c] = add_rec<BASIS>(u, rt);
         Xb[N + lane + c * T] = x[c];
     }
     const __amdgpu_buffer_rsrc_t rsrc = out_window(ob, cnt);
@@ -174,8 +209,8 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const uin
 // per-round scalar work is kept to a few instructions, because in the group
 // form every wavefront repeats it. WAVE: one wavefront, no barriers (LDS
 // operations of a wavefront complete in order).
-template <int KIND, int SPL, bool WAVE>
-__device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const uint32_t *__restrict__ rtb,
+template <int KIND, int SPL, bool WAVE, bool BASIS>
+__device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecTable &rt,
                                            const uint32_t *__restrict__ otb, uint32_t N, uint32_t M,
                                            uint32_t sh1, uint32_t sh2, uint32_t mask, uint32_t W,
                                            uint32_t L, uint64_t n, gu32 *__restrict__ out,
@@ -199,7 +234,7 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const uint3
         const uint32_t room = (L - N - span - base) / W + 1;
         const uint32_t k = full < room ? (uint32_t)full : room;
         for (uint32_t j = 0; j < k; ++j) {
-            round_steps<KIND, SPL>(X + base, rtb, otb, N, M, sh1, sh2, mask, lane, T, W, ob);
+            round_steps<KIND, SPL, BASIS>(X + base, rt, otb, N, M, sh1, sh2, mask, lane, T, W, ob);
             if (!WAVE)
                 __syncthreads();
             base += W;
@@ -215,7 +250,7 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const uint3
                 __syncthreads();
             base = 0;
         }
-        round_steps<KIND, SPL>(X + base, rtb, otb, N, M, sh1, sh2, mask, lane, T, rem, ob);
+        round_steps<KIND, SPL, BASIS>(X + base, rt, otb, N, M, sh1, sh2, mask, lane, T, rem, ob);
         if (!WAVE)
             __syncthreads();
         base += rem;
@@ -243,13 +278,13 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const uint3
 // slot, then the window X of L words.
 // ---------------------------------------------------------------------------
 
-template <int KIND, bool WAVE>
-__device__ __forceinline__ void run_item(uint32_t spl, uint32_t *X, const uint32_t *rtb, const uint32_t *otb,
+template <int KIND, bool WAVE, bool BASIS>
+__device__ __forceinline__ void run_item(uint32_t spl, uint32_t *X, const RecTable &rt, const uint32_t *otb,
                                          const GenRecord &g, uint32_t W, uint32_t L, uint64_t n, gu32 *out,
                                          uint32_t *state, uint32_t lane, uint32_t T)
 {
 #define MTGP_RUN(S) \
-    run_stream<KIND, S, WAVE>(X, rtb, otb, g.N, g.M, g.sh1, g.sh2, g.mask, W, L, n, out, state, lane, T)
+    run_stream<KIND, S, WAVE, BASIS>(X, rt, otb, g.N, g.M, g.sh1, g.sh2, g.mask, W, L, n, out, state, lane, T)
     if (WAVE) {
         switch (spl) {
         case 1: MTGP_RUN(1); break;
@@ -270,7 +305,7 @@ __device__ __forceinline__ void run_item(uint32_t spl, uint32_t *X, const uint32
 #undef MTGP_RUN
 }
 
-template <bool WAVE>
+template <bool WAVE, bool BASIS>
 __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict__ recs, uint32_t *__restrict__ states,
                                                     const WorkItem *__restrict__ items, uint32_t nitems,
                                                     uint32_t *counters, WorkItem single, uint32_t L)
@@ -343,6 +378,7 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             rtb[lane] = g.rec[lane];
             otb[lane] = kind == 0 ? g.tmp[lane] : g.flt[lane];
         }
+        const RecTable rt = {rtb, g.rec[1], g.rec[2], g.rec[4], g.rec[8]};
         if (!WAVE)
             __syncthreads();
 
@@ -354,15 +390,15 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
             out += N;
         }
         if (kind == kKindU32)
-            run_item<kKindU32, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindU32, WAVE, BASIS>(spl, X, rt, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindF12)
-            run_item<kKindF12, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindF12, WAVE, BASIS>(spl, X, rt, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindF01)
-            run_item<kKindF01, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindF01, WAVE, BASIS>(spl, X, rt, otb, g, W, L, it.n, out, state, lane, T);
         else if (kind == kKindNormal)
-            run_item<kKindNormal, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindNormal, WAVE, BASIS>(spl, X, rt, otb, g, W, L, it.n, out, state, lane, T);
         else
-            run_item<kKindRaw, WAVE>(spl, X, rtb, otb, g, W, L, it.n, out, state, lane, T);
+            run_item<kKindRaw, WAVE, BASIS>(spl, X, rt, otb, g, W, L, it.n, out, state, lane, T);
         if (!WAVE)
             __syncthreads();   // the next item overwrites the window and tables
     }
@@ -390,12 +426,20 @@ hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkIt
     const uint32_t L = (uint32_t)shape.lds_words;
     const uint32_t units = shape.mode == kModeGroup ? 1u : (uint32_t)(shape.threads / 64);
     const size_t lds = (size_t)units * (kTableWords + L) * sizeof(uint32_t);
-    if (shape.mode == kModeGroup)
-        hipLaunchKernelGGL(mtgp_kernel<false>, grid, block, lds, stream, recs, states, items, nitems, counters,
-                           single, L);
-    else
-        hipLaunchKernelGGL(mtgp_kernel<true>, grid, block, lds, stream, recs, states, items, nitems, counters,
-                           single, L);
+#define MTGP_LAUNCH(W, B) \
+    hipLaunchKernelGGL((mtgp_kernel<W, B>), grid, block, lds, stream, recs, states, items, nitems, counters, single, L)
+    if (shape.mode == kModeGroup) {
+        if (shape.rec_basis)
+            MTGP_LAUNCH(false, true);
+        else
+            MTGP_LAUNCH(false, false);
+    } else {
+        if (shape.rec_basis)
+            MTGP_LAUNCH(true, true);
+        else
+            MTGP_LAUNCH(true, false);
+    }
+#undef MTGP_LAUNCH
     return hipGetLastError();
 }
 
@@ -601,12 +645,16 @@ hipError_t launch_jumps(const JumpItem *d_items, const JumpItem *h_items, uint32
 hipError_t opt_in_lds(size_t bytes)
 {
     const int b = (int)bytes;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mtgp_kernel<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&mtgp_kernel<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    return e;
+    const void *kernels[] = {reinterpret_cast<const void *>(&mtgp_kernel<false, false>),
+                             reinterpret_cast<const void *>(&mtgp_kernel<false, true>),
+                             reinterpret_cast<const void *>(&mtgp_kernel<true, false>),
+                             reinterpret_cast<const void *>(&mtgp_kernel<true, true>)};
+    for (const void *k : kernels) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace mtgp_impl

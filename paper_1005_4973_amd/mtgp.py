@@ -24,6 +24,10 @@ PHASE_ALL = 0
 PHASE_PREPARE = 1
 PHASE_GENERATE = 2
 
+MODE_GROUP = 0
+MODE_WAVE = 1
+MODE_REC_BASIS = 4   # flag: recursion table from its F2 basis in registers (not an LDS lookup)
+
 KIND_UINT32 = 0
 KIND_FLOAT32_1TO2 = 1
 KIND_FLOAT32_0TO1 = 2

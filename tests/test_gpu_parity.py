@@ -209,10 +209,13 @@ def test_batch_rejects_bad_requests(M):
 # Launch shapes: every valid shape gives the same bits
 # ---------------------------------------------------------------------------
 
+RB = 4   # mode flag: recursion table from its F2 basis in registers instead of the LDS lookup
 SHAPES = [
     (0, 64, 1, 0, 0), (0, 64, 4, 0, 0), (0, 256, 1, 0, 0), (0, 256, 4, 0, 0), (0, 512, 2, 0, 0),
     (0, 1024, 1, 0, 0), (0, 256, 4, 24000, 0), (1, 64, 1, 0, 0), (1, 64, 4, 0, 0), (1, 256, 6, 0, 0),
     (1, 128, 16, 0, 0), (1, 256, 8, 4096, 3),
+    (0 | RB, 64, 4, 0, 0), (0 | RB, 256, 1, 0, 0), (0 | RB, 512, 2, 0, 0), (0 | RB, 1024, 1, 0, 0),
+    (1 | RB, 64, 1, 0, 0), (1 | RB, 256, 6, 0, 0), (1 | RB, 128, 16, 0, 0),
 ]
 
 
@@ -247,10 +250,10 @@ def test_wide_workgroups_long_streams(M):
     import torch
     params = I.draw_param_sets([11213, 11213, 521], 66, I.M_POLICY_WIDE) + I.draw_param_sets([23209], 67)
     seeds = I.state_seeds(len(params))
-    for threads in (512, 1024):
-        say(f"threads {threads}")
+    for mode, threads in ((0, 512), (0, 1024), (RB, 512)):
+        say(f"mode {mode} threads {threads}")
         b = M.Batch(params, seeds)
-        b.set_launch(0, threads, 1, 0, 0)
+        b.set_launch(mode, threads, 1, 0, 0)
         states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
         for n in (300007, 4099):
             reqs = [(g, g % 3, n) for g in range(len(params))]
@@ -259,7 +262,7 @@ def test_wide_workgroups_long_streams(M):
             torch.cuda.synchronize()
             for (g, k, n), buf in zip(reqs, bufs):
                 ref = O.generate(params[g], states[g], n, k)
-                np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"threads={threads} gen={g} n={n}")
+                np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"mode={mode} threads={threads} gen={g} n={n}")
         for g in range(len(params)):
             np.testing.assert_array_equal(b.get_state(g)[0], states[g])
         b.close()
@@ -299,7 +302,8 @@ def test_single_generator_shapes(M):
     (ps,), _ = I.single_stream()
     st = O.seed_state(21, ps.mexp)
     g = M.Generator(ps, 21)
-    for sh in [(0, 64, 4, 0), (0, 256, 1, 0), (0, 1024, 1, 2000), (1, 64, 16, 0), (1, 64, 4, 1000), (-1, 0, 1, 0)]:
+    for sh in [(0, 64, 4, 0), (0, 256, 1, 0), (0, 1024, 1, 2000), (1, 64, 16, 0), (1, 64, 4, 1000),
+               (0 | RB, 256, 4, 0), (1 | RB, 64, 8, 0), (-1, 0, 1, 0)]:
         g.set_launch(*sh)
         out = g.generate(7777, I.KIND_F01)
         np.testing.assert_array_equal(host_bits(out), O.generate(ps, st, 7777, I.KIND_F01), err_msg=str(sh))
@@ -383,6 +387,17 @@ def test_plan_split_jump_ahead(M):
         torch.cuda.synchronize()
         for g in range(len(params)):
             np.testing.assert_array_equal(host_bits(eb[g])[:333], O.generate(params[g], states[g], 333, 1))
+    # the same requests as a plan with the recursion table's basis form
+    b.set_launch(RB, 256, 1, 0, 0)
+    plan2 = b.plan([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+    say("split plan, basis form")
+    plan2.launch()
+    torch.cuda.synchronize()
+    for (g, k, n), buf in zip(reqs, bufs):
+        ref = O.generate(params[g], states[g], n, k)
+        np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"basis form gen={g} mexp={params[g].mexp}")
+    plan2.close()
+    b.set_launch(-1)
     for g in range(len(params)):
         np.testing.assert_array_equal(b.get_state(g)[0], states[g])
     # replacing a split generator's state makes the plan stale
@@ -437,7 +452,7 @@ def test_autotune_leaves_streams_and_keeps_parity(M):
     say("autotune")
     best = b.autotune(reqs, reps=2)
     say(f"autotune chose {best}")
-    assert best["trials"] >= 2 and best["ms"] > 0
+    assert best["trials"] >= 2 and best["ms"] > 0 and best["mode"] in (-1, 0, 1, RB, 1 | RB)
     for g in range(len(params)):
         words, consumed = b.get_state(g)
         np.testing.assert_array_equal(words, states[g])
