@@ -211,12 +211,15 @@ def headline(args, torch, I, mtgp):
     batch.close()
     del out
     torch.cuda.empty_cache()
+    mode = tuning["mode"]
+    kernel = "mtgp_kernel<{}, {}>".format("true" if mode >= 0 and mode & 1 else "false",
+                                          "true" if mode >= 0 and mode & 4 else "false")
     return params, n, kinds, tuning, {
         "value": round(numbers_per_step * args.steps / dt / 1e9, 3),
         "ms_per_step": round(dt / args.steps * 1e3, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(tuning),
-                     "kernel": "mtgp_kernel<false> (persistent generation over jump-ahead segments)",
+                     "kernel": kernel + " (persistent generation over jump-ahead segments)",
                      "avg_launch_ms": round(avg_gen_s * 1e3, 4),
                      "avg_prepare_ms": round(sum(prep_ms) / len(prep_ms), 4),
                      "alg_bytes_per_launch": alg_bytes,
