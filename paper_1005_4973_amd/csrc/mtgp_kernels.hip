@@ -69,31 +69,32 @@ __device__ __forceinline__ uint32_t output_word(uint32_t x, uint32_t tv)
     }
 }
 
-// DPP control quad_perm(1,0,3,2): lanes 2m and 2m+1 exchange values.
-constexpr int kDppSwapPairs = 0xb1;
+// DPP controls quad_perm(0,0,2,2) and quad_perm(1,1,3,3): lanes 2m and 2m+1
+// both read lane 2m, or both read lane 2m+1.
+constexpr int kDppPairFirst = 0xa0;
+constexpr int kDppPairSecond = 0xf5;
 
 // -2 ln 2: r^2 = -2 ln(u1) = -2 ln 2 * log2(u1)
 constexpr float kMinus2Ln2 = -1.3862943611198906f;
 
 // Box-Muller on the float [1,2) bits `f` of this lane and of its pair
-// partner (lane ^ 1); the even lane holds the first of the pair and returns
-// r cos(theta), the odd lane r sin(theta). 2 - a and b - 1 are exact in
-// binary32, so the logarithm's argument lies in (0, 1] and the angle is
-// taken in revolutions by the hardware sine (input t means sin(2 pi t)),
-// with cos(2 pi t) = sin(2 pi (t + 1/4)); t + 1/4 is exact too, a multiple
-// of 2^-23 below 1.25. The hardware base-2 logarithm, square root and sine
-// are used directly: over all 2^23 inputs of each, r is within 4.7e-7 and
-// the sine and cosine within 1.3e-7 of the exact values (measured
-// exhaustively on gfx950), so |z| is within about 1.5e-6.
-__device__ __forceinline__ uint32_t box_muller(uint32_t f, uint32_t lane)
+// partner (lane ^ 1); the even lane holds the first of the pair, a, and
+// returns r cos(theta), the odd lane r sin(theta). Both lanes of a pair read
+// a and b from the pair's lanes (a DPP broadcast within the pair). 2 - a is
+// exact in binary32, so the logarithm's argument lies in (0, 1]; the angle is
+// taken in revolutions by the hardware sine (input t means sin(2 pi t)), with
+// t = b - 1 for the sine and t = b - 3/4 = (b - 1) + 1/4 for the cosine
+// (cos(2 pi x) = sin(2 pi (x + 1/4))); both are exact, multiples of 2^-23
+// in [0, 1.25). The hardware base-2 logarithm, square root and sine are used
+// directly: over all 2^23 inputs of each, r is within 4.7e-7 and the sine and
+// cosine within 1.3e-7 of the exact values (measured exhaustively on gfx950),
+// so |z| is within about 1.5e-6.
+__device__ __forceinline__ uint32_t box_muller(uint32_t f, float shift, float two)
 {
-    const uint32_t p = (uint32_t)__builtin_amdgcn_mov_dpp((int)f, kDppSwapPairs, 0xf, 0xf, true);
-    const bool odd = lane & 1u;
-    const float a = __uint_as_float(odd ? p : f);
-    const float b = __uint_as_float(odd ? f : p);
-    const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(2.0f - a));
-    const float t = (b - 1.0f) + (odd ? 0.0f : 0.25f);
-    return __float_as_uint(r * __builtin_amdgcn_sinf(t));
+    const float a = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)f, kDppPairFirst, 0xf, 0xf, true));
+    const float b = __uint_as_float((uint32_t)__builtin_amdgcn_mov_dpp((int)f, kDppPairSecond, 0xf, 0xf, true));
+    const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(two - a));
+    return __float_as_uint(r * __builtin_amdgcn_sinf(b + shift));
 }
 
 // Output stores go through a buffer resource covering exactly the round's
@@ -166,7 +167,7 @@ template <int KIND, int SPL, bool BASIS>
 __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const RecTable &rt,
                                             const uint32_t *__restrict__ otb, uint32_t N, uint32_t M,
                                             uint32_t sh1, uint32_t sh2, uint32_t mask, uint32_t lane,
-                                            uint32_t T, uint32_t cnt, gu32 *__restrict__ ob)
+                                            uint32_t T, uint32_t cnt, gu32 *__restrict__ ob, float two)
 {
     uint32_t xi[SPL], xi1[SPL], xt[SPL], xm[SPL];
 #pragma unroll
@@ -193,12 +194,14 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const Rec
         Xb[N + lane + c * T] = x[c];
     }
     const __amdgpu_buffer_rsrc_t rsrc = out_window(ob, cnt);
+    // angle offset of the normal kind: b - 1 (sine, odd lanes), b - 3/4 (cosine, even lanes)
+    const float shift = (lane & 1u) ? -1.0f : -0.75f;
 #pragma unroll
     for (int c = 0; c < SPL; ++c) {
         const uint32_t k = lane + c * T;
         uint32_t o = output_word<KIND>(x[c], tv[c]);
         if constexpr (KIND == kKindNormal)
-            o = box_muller(o, lane);   // steps k and k^1 are lanes lane and lane^1 (T is even)
+            o = box_muller(o, shift, two);   // steps k and k^1 are lanes lane and lane^1 (T is even)
         __builtin_amdgcn_raw_buffer_store_b32(o, rsrc, (int)(k * 4u), 0, kStoreNT);
     }
 }
@@ -217,6 +220,10 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecTa
                                            uint32_t *__restrict__ state, uint32_t lane, uint32_t T)
 {
     const uint32_t span = T * SPL;   // slots written per round
+    // 2.0 in a vector register (normal kind), so that 2 - a can read a through DPP
+    float two = 2.0f;
+    if constexpr (KIND == kKindNormal)
+        asm("v_mov_b32 %0, 2.0" : "=v"(two));
     uint64_t full = n / W;
     const uint32_t rem = (uint32_t)(n - full * W);
     uint32_t base = 0;
@@ -234,7 +241,7 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecTa
         const uint32_t room = (L - N - span - base) / W + 1;
         const uint32_t k = full < room ? (uint32_t)full : room;
         for (uint32_t j = 0; j < k; ++j) {
-            round_steps<KIND, SPL, BASIS>(X + base, rt, otb, N, M, sh1, sh2, mask, lane, T, W, ob);
+            round_steps<KIND, SPL, BASIS>(X + base, rt, otb, N, M, sh1, sh2, mask, lane, T, W, ob, two);
             if (!WAVE)
                 __syncthreads();
             base += W;
@@ -250,7 +257,7 @@ __device__ __forceinline__ void run_stream(uint32_t *__restrict__ X, const RecTa
                 __syncthreads();
             base = 0;
         }
-        round_steps<KIND, SPL, BASIS>(X + base, rt, otb, N, M, sh1, sh2, mask, lane, T, rem, ob);
+        round_steps<KIND, SPL, BASIS>(X + base, rt, otb, N, M, sh1, sh2, mask, lane, T, rem, ob, two);
         if (!WAVE)
             __syncthreads();
         base += rem;
