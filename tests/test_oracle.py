@@ -428,6 +428,21 @@ def test_normals_special_values():
     np.testing.assert_allclose(z[6:8], [-r_max, 0.0], atol=1e-12)  # angle pi
 
 
+def test_box_muller_binary32_arguments_are_exact():
+    """The device evaluates the transform's arguments in binary32: 2 - a,
+    b - 1 (sine) and b - 3/4 (cosine, the sine a quarter turn on). For every
+    one of the 2^23 float [1,2) values each is exact, and b - 3/4 equals
+    (b - 1) + 1/4, so the angle the hardware sine receives carries no
+    rounding; the normals' tolerance only has to cover the log, square root
+    and sine themselves."""
+    x = (np.uint32(0x3F800000) | np.arange(1 << 23, dtype=np.uint32)).view(np.float32)
+    x64 = x.astype(np.float64)
+    for got, want in ((np.float32(2.0) - x, 2.0 - x64), (x - np.float32(1.0), x64 - 1.0),
+                      (x - np.float32(0.75), x64 - 0.75)):
+        np.testing.assert_array_equal(got.astype(np.float64), want)
+    np.testing.assert_array_equal((x - np.float32(1.0)) + np.float32(0.25), x - np.float32(0.75))
+
+
 def test_normals_are_standard_normal_and_consume_n_steps():
     from scipy import stats
     params = I.draw_param_sets([11213] * 4, 91)
