@@ -956,10 +956,12 @@ static int generate_split(mtgp_t *g, uint64_t n, void *out, hipStream_t s, uint3
                             : reinterpret_cast<uint64_t>(g->d_seg + (size_t)(k - 1) * N);
         }
         // the launch shape of the segments: 256-lane workgroups, as many per
-        // CU as the segments need (up to 8), each with an even share of LDS
+        // CU as the segments need (up to 8), each with an even share of LDS,
+        // and the generator's recursion-table form
         sh.mode = kModeGroup;
         sh.threads = 256;
         sh.spl = 4;
+        sh.rec_basis = g->shape.rec_basis;
         sh.grid = 1;
         sh.lds_words = 1;
         const uint32_t cus = (uint32_t)std::max(1, g->cu_count);

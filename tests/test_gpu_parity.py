@@ -565,4 +565,8 @@ def test_single_generator_split_calls(M):
         g.set_state(st2, 0)
         out = g.generate(100000, 0)
         np.testing.assert_array_equal(host_bits(out), O.generate(ps, st2, 100000, 0))
+        # the segments take the generator's recursion-table form
+        g.set_launch(RB, 256, 4, 0)
+        out = g.generate(100000, 1)
+        np.testing.assert_array_equal(host_bits(out), O.generate(ps, st2, 100000, 1))
         g.close()
