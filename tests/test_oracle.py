@@ -75,8 +75,10 @@ def test_hand_trace_mask_and_tempering_shifts():
 # Two readings of the paper agree: C form (oracle) vs matrix form (pyref).
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mexp", [89, 107, 127, 521, 607])
+@pytest.mark.parametrize("mexp", [65, 89, 107, 127, 521, 607, 608])
 def test_c_form_equals_matrix_form(mexp):
+    # 65 and 608 are the extremes of the mask: r = 31 (one bit of x_i kept)
+    # and r = 0 (the whole word)
     for s in range(3):
         ps = I.draw_param_set(mexp, I.SplitMix64(31 * mexp + s), I.M_POLICY_FULL)
         st = O.seed_state(100 + s, mexp)
