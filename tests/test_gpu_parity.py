@@ -64,8 +64,12 @@ def test_single_stream_all_kinds(M):
         g.close()
 
 
-@pytest.mark.parametrize("mexp", [89, 107, 521, 2203, 11213, 23209, 44497])
+@pytest.mark.parametrize("mexp", [65, 89, 107, 521, 2203, 11213, 23209, 44497, 65536])
 def test_m_sweep_and_ragged_lengths(M, mexp):
+    """Every M class at the edges of its range (2, 3, N/2, N-3 .. N-1) and
+    lengths around N, W and their multiples, for the three released state
+    sizes, small ones, and the extremes of the accepted range (p = 65: N = 3,
+    r = 31; p = 65536: N = 2048, r = 0, no mask)."""
     N = O.nwords(mexp)
     Ms = sorted({2, 3, N // 2, N - 3, N - 2, N - 1} & set(range(2, N)))
     base = I.draw_param_set(mexp, I.SplitMix64(mexp + 1), I.M_POLICY_FULL)
