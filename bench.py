@@ -251,6 +251,22 @@ def batched_uneven(torch, I, mtgp):
     torch.cuda.synchronize()
     ms_p = (time.perf_counter() - t0) * 1e3
     plan.close()
+    # critical path: the segment with the most rounds under the tuned shape and
+    # split limit, timed alone (same shape, no split, one workgroup)
+    r_max, crit = 0, None
+    for r in reqs:
+        ps = params[r.gen]
+        W = round_width(state_words(ps.mexp), ps.pos, tuning)
+        rounds = -(-r.n // W)
+        S = -(-rounds // tuning["split_rounds"]) if tuning["split_rounds"] else 1
+        J = -(-r.n // S)
+        if -(-J // W) > r_max:
+            r_max, crit = -(-J // W), (r, J)
+    batch.set_split(0)
+    (r, J) = crit
+    p1 = batch.plan([(r.gen, r.kind, J, base + 4 * r.offset)])
+    ms_c = timed_ms(torch, lambda: p1.launch())
+    p1.close()
     batch.close()
     del out
     torch.cuda.empty_cache()
@@ -259,8 +275,29 @@ def batched_uneven(torch, I, mtgp):
     return {"generators": G, "numbers": tot,
             "batched": {"ms": round(ms_b, 3), "G_numbers_s": round(tot / ms_b / 1e6, 2), **roof(alg, ms_b / 1e3),
                         "autotuned": tuning, "autotune_s": round(tune_s, 1)},
+            "critical_path": {"segment_rounds": r_max, "mexp": params[crit[0].gen].mexp, "segment_outputs": crit[1],
+                              "alone_ms": round(ms_c, 3), "makespan_over_bound": round(ms_b / ms_c, 2)},
             "plain_one_launch_per_request": {"ms": round(ms_p, 1), "G_numbers_s": round(tot / ms_p / 1e6, 3)},
             "speedup_batched_vs_plain": round(ms_p / ms_b, 1)}
+
+
+def state_words(mexp):
+    return (mexp + 31) // 32
+
+
+def round_width(N, M, tuning):
+    """Steps a round of this generator computes under a tuned launch shape:
+    W = min(N - M, lanes * s), s the largest steps per lane allowed by the
+    shape with lanes * s <= N - M (the library's own rule)."""
+    mode = tuning["mode"]
+    if mode < 0:
+        wave, threads, cap = False, 256, 4
+    else:
+        wave, threads, cap = bool(mode & 1), tuning["threads"], tuning["spl"]
+    lanes = 64 if wave else threads
+    cands = (16, 12, 8, 6, 4, 2, 1) if wave else (4, 2, 1)
+    s = next((c for c in cands if c <= cap and lanes * c <= N - M), 1)
+    return min(N - M, lanes * s)
 
 
 def large_states(torch, I, mtgp):
