@@ -42,7 +42,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("batched_uneven", "large_states", "normals", "single_stream", "serving", "param_search")
+SECTIONS = ("batched_uneven", "large_states", "large_states_wide_m", "normals", "single_stream", "serving",
+            "param_search")
 
 
 def parse():
@@ -324,6 +325,37 @@ def large_states(torch, I, mtgp):
     return res
 
 
+def large_states_wide_m(torch, I, mtgp):
+    """Sensitivity of the large-state batch to the M rule: 256 MTGP-23209
+    generators x 2^24 with M uniform in [2, N-2]. The generators with small
+    N - M have millions of dependent rounds; the tuned plan splits them into
+    jump-ahead segments. Reported with the segment that bounds the makespan."""
+    params, n = I.large_states_wide_m(23209)
+    G, N = len(params), 726
+    batch = mtgp.Batch(params, I.state_seeds(G))
+    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+    rq = [(g, 0, n, out.data_ptr() + 4 * g * n) for g in range(G)]
+    t0 = time.perf_counter()
+    tuning = batch.autotune(rq, reps=1)
+    tune_s = time.perf_counter() - t0
+    plan = batch.plan(rq)
+    ms = timed_ms(torch, lambda: plan.launch(), reps=5, warmup=1)
+    plan.close()
+    widths = [round_width(N, ps.pos, tuning) for ps in params]
+    rounds = [-(-n // w) for w in widths]
+    S = [-(-r // tuning["split_rounds"]) if tuning["split_rounds"] else 1 for r in rounds]
+    seg_len = [-(-n // s) for s in S]
+    seg_rounds = [-(-j // w) for j, w in zip(seg_len, widths)]
+    batch.close()
+    del out
+    torch.cuda.empty_cache()
+    alg = G * (4 * n + 8 * N + 256)
+    return {"generators": G, "numbers": G * n, "M_rule": "uniform in [2, N-2]", "min_N_minus_M": min(N - p.pos for p in params),
+            "ms": round(ms, 3), "G_numbers_s": round(G * n / ms / 1e6, 2), **roof(alg, ms / 1e3),
+            "segments": sum(S), "max_segment_rounds": max(seg_rounds), "unsplit_max_rounds": max(rounds),
+            "autotuned": tuning, "autotune_s": round(tune_s, 1)}
+
+
 def normals(torch, I, mtgp):
     """128 MTGP-11213 generators x 2^22 Gaussian deviates (Box-Muller on pairs of
     float [1,2) outputs), one tuned split plan replayed."""
@@ -478,8 +510,12 @@ def main():
         res["cpu_baseline"] = cpu_baseline(params, n, kinds, threads)
         log(f"cpu baseline: {res['cpu_baseline']['value']} G numbers/s")
     sections = [s for s in args.sections.split(",") if s]
-    fns = {"batched_uneven": batched_uneven, "large_states": large_states, "normals": normals,
+    fns = {"batched_uneven": batched_uneven, "large_states": large_states,
+           "large_states_wide_m": large_states_wide_m, "normals": normals,
            "single_stream": single_stream, "serving": serving, "param_search": param_search}
+    unknown = [name for name in sections if name not in fns]
+    if unknown:
+        raise SystemExit(f"unknown sections: {unknown}")
     for name in sections:
         t0 = time.perf_counter()
         res[name] = fns[name](torch, I, mtgp)

@@ -226,7 +226,8 @@ void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's la
  * Autotuner for a request list (unique generators, as for plans). Times `reps`
  * plan launches on `stream` for each candidate configuration -- the automatic
  * launch shape with no split and with split limits halving from the longest
- * request's round count down to 128 rounds, then, at the best split limit,
+ * request's round count down to 128 rounds (seven halvings, then more only
+ * while each one is the fastest so far), then, at the best split limit,
  * workgroup forms of 128/256/512/1024 lanes with 1-4 steps per lane and the
  * wavefront form, then the best of these with the other recursion-table
  * form (MTGP_MODE_REC_BASIS) -- and keeps the fastest (a later candidate must be at least

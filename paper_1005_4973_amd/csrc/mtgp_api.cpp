@@ -1512,7 +1512,17 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     Cand c0{true, had_shape, 0, 0.0f};
     trial(c0);
     tried.push_back(c0);
-    for (uint64_t sr = rmax / 2; sr >= 128 && tried.size() < 8 && device_ok; sr /= 2) {
+    // seven halvings; beyond them (requests with millions of rounds) the sweep
+    // goes on while each halving is the fastest configuration so far
+    for (uint64_t sr = rmax / 2; sr >= 128 && tried.size() < 20 && device_ok; sr /= 2) {
+        if (tried.size() >= 8) {
+            const float last = tried.back().ms;
+            bool fastest = last > 0;
+            for (const Cand &t : tried)
+                fastest = fastest && !(t.ms > 0 && t.ms < last);
+            if (!fastest)
+                break;
+        }
         Cand c{true, had_shape, (uint32_t)sr, 0.0f};
         trial(c);
         tried.push_back(c);

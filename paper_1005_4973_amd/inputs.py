@@ -173,6 +173,14 @@ def large_states(mexp: int, count: int = 256) -> Tuple[List[ParamSet], int]:
     return draw_param_sets([mexp] * count, 3000 + (mexp == 44497), M_POLICY_PAPER), 1 << 24
 
 
+def large_states_wide_m(mexp: int = 23209, count: int = 256) -> Tuple[List[ParamSet], int]:
+    """The large-state batch with M drawn from [2, N-2] (the single-stream
+    configuration's rule) instead of the paper's: some generators get N - M of
+    a few words, i.e. millions of dependent rounds for 2^24 outputs."""
+    assert mexp in (23209, 44497)
+    return draw_param_sets([mexp] * count, 3002 + (mexp == 44497), M_POLICY_WIDE), 1 << 24
+
+
 @dataclass
 class Request:
     gen: int
