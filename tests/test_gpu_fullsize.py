@@ -1,9 +1,9 @@
 """Parity at the workloads' full sizes, in the configurations the benchmark
 times: autotuned jump-ahead plans for the 128 x 2^22 headline, the 256 x
-2^24 large-state batches and the 4096-request uneven batch (every output of
-every generator, copied back in chunks), and the native request loop over
-65536 states (every request). The oracle runs on host threads (its C
-calls release the GIL).
+2^24 large-state batches (under the paper's M rule and the wide one) and the
+4096-request uneven batch (every output of every generator, copied back in
+chunks), and the native request loop over 65536 states (every request). The
+oracle runs on host threads (its C calls release the GIL).
 """
 import os
 from concurrent.futures import ThreadPoolExecutor
@@ -103,6 +103,43 @@ def test_large_states_full_size(M, mexp, split):
     say(f"p={mexp}: all {G} streams equal")
     for g in range(G):
         np.testing.assert_array_equal(b.get_state(g)[0], states[g], err_msg=f"p={mexp} state gen={g}")
+    plan.close()
+    b.close()
+    del out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_large_states_wide_m_full_size(M):
+    """The M-rule sensitivity batch (256 MTGP-23209 generators, M in [2, N-2],
+    2^24 uint32 each) as the autotuned plan: thousands of jump-ahead segments,
+    many of them for generators whose rounds are a few words wide; every
+    stream and every end state compared."""
+    import torch
+    params, n = I.large_states_wide_m(23209)
+    G = len(params)
+    seeds = I.state_seeds(G)
+    b = M.Batch(params, seeds)
+    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+    reqs = [(g, 0, n, out.data_ptr() + 4 * g * n) for g in range(G)]
+    tuning = b.autotune(reqs, reps=1)
+    say(f"wide-M tuning {tuning}")
+    plan = b.plan(reqs)
+    plan.launch()
+    torch.cuda.synchronize()
+    states = {g: O.seed_state(seeds[g], 23209) for g in range(G)}
+    chunk = 16
+    with pool() as ex:
+        for g0 in range(0, G, chunk):
+            gens = range(g0, min(G, g0 + chunk))
+            host = device_words(out, g0 * n, len(gens) * n)
+            refs = list(ex.map(lambda g: O.generate(params[g], states[g], n, 0), gens))
+            for g, ref in zip(gens, refs):
+                np.testing.assert_array_equal(host[(g - g0) * n:(g - g0 + 1) * n], ref,
+                                              err_msg=f"gen={g} N-M={726 - params[g].pos}")
+    say(f"wide M: all {G} streams equal")
+    for g in range(G):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g], err_msg=f"state gen={g}")
     plan.close()
     b.close()
     del out
