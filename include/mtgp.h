@@ -258,8 +258,8 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
  *   mode | MTGP_MODE_REC_BASIS: the recursion table rec[u & 0xf] is evaluated
  *           from its four F2 basis words in registers instead of read from
  *           LDS: more vector instructions per step, but no lookup on the
- *           chain of a round (faster where one generator's chain of rounds
- *           sets the launch time, slower where many generators share a CU).
+ *           chain of a round. Which form is faster depends on the workload;
+ *           the autotuner tries both.
  * Each generator uses the largest supported s <= spl with lanes*s <= N - M
  * (lanes = threads in mode 0, 64 in mode 1), so a round computes
  * W = min(N - M, lanes*s) steps (section 3.2). lds_words is the LDS window per

@@ -129,9 +129,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_window(gu32 *p, uint32_t c
 //       b < 4 of u -- four sign-extended bit masks and four 3-input bit
 //       operations against basis words in scalar registers (8 instructions,
 //       no lookup on the chain).
-// Throughput-bound launches (many generators per CU) run faster with the
-// lookup, launches whose time is one generator's chain of rounds with the
-// basis form; the launch shape chooses.
+// Which is faster depends on the launch (measured on gfx950: the lookup for
+// batches of like generators filling every CU and for a single generator,
+// the basis form for a mixed-period batch whose workgroups are wider than
+// its smallest items' rounds); the launch shape chooses.
 struct RecTable {
     const uint32_t *lds;          // rec[0..16) in LDS
     uint32_t b0, b1, b2, b3;      // rec[1], rec[2], rec[4], rec[8]
