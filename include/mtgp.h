@@ -162,7 +162,12 @@ mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds,
  * Serve `nreq` requests in one persistent kernel launch on `stream`. A
  * generator may appear at most once per call (requests for one generator
  * must be split across calls, which run in stream order). Requests with
- * n = 0 are skipped. Returns MTGP_EINVAL for a bad generator index, kind,
+ * n = 0 are skipped. With a split limit set (mtgp_batch_set_split) and a
+ * request longer than it, the call runs as a one-off plan of jump-ahead
+ * segments: it then waits for the batch's last stream (and, the first time
+ * for a generator, reads its raw words back to find the annihilator) before
+ * the launch is enqueued; the plan is kept until the next such call or
+ * mtgp_batch_destroy. Returns MTGP_EINVAL for a bad generator index, kind,
  * duplicate generator or misaligned output.
  */
 int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream);
@@ -191,7 +196,8 @@ typedef struct mtgp_plan mtgp_plan_t;
 
 /*
  * Jump-ahead for plans (the paper's section 7 discusses jumping ahead).
- * With max_rounds > 0, mtgp_batch_plan_create splits every request whose
+ * With max_rounds > 0, mtgp_batch_plan_create (and mtgp_batch_generate, as a
+ * one-off plan) splits every request whose
  * generator would need more than max_rounds rounds into S segments of J
  * outputs that run concurrently: segment k starts from the state F^{kJ} S,
  * computed on the GPU at each launch as the XOR of the states S, F S, ...

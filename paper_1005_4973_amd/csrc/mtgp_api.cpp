@@ -5,6 +5,7 @@
 #include "../../include/mtgp.h"
 #include "mtgp_f2.h"
 #include "mtgp_internal.h"
+#include "mtgp_host.h"
 
 static_assert(mtgp_impl::kModeRecBasis == MTGP_MODE_REC_BASIS, "launch mode flag");
 
@@ -236,6 +237,7 @@ struct mtgp_batch {
     std::vector<uint64_t> epoch;               // bumped by set_state
     std::vector<f2::Poly> psi;                 // annihilator of the generator's orbit (empty: none)
     std::vector<uint64_t> psi_epoch;           // epoch + 1 when psi was computed, 0 if never
+    mtgp_plan *eager_plan = nullptr;           // the last eager call run as a one-off split plan
 };
 
 struct mtgp_plan {
@@ -1192,11 +1194,22 @@ void mtgp_batch_destroy(mtgp_batch_t *b)
 {
     if (!b)
         return;
+    mtgp_plan_destroy(b->eager_plan);   // waits for the batch's last stream
+    b->eager_plan = nullptr;
     (void)hipStreamSynchronize(b->last);
     batch_free(b);
 }
 
 int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream)
+{
+    return mtgp_impl::batch_generate(b, reqs, nreq, stream, true);
+}
+
+}  // extern "C"
+
+namespace mtgp_impl {
+
+int batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream, bool allow_split)
 {
     if (validate_requests(b, reqs, nreq, true) != MTGP_OK)
         return fail(MTGP_EINVAL);
@@ -1207,6 +1220,28 @@ int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     LaunchShape shape;
     if (resolve_shape(b, items, shape) != MTGP_OK)
         return fail(MTGP_EINVAL);
+    if (allow_split && b->split_rounds > 0) {
+        bool long_request = false;
+        for (const WorkItem &it : items) {
+            const GenRecord &r = b->recs[it.gen];
+            const uint32_t W = round_width(r.N, r.M, shape);
+            long_request = long_request || (it.n + W - 1) / W > b->split_rounds;
+        }
+        if (long_request) {
+            // the call as a one-off plan of jump-ahead segments, kept until the
+            // next such call or the batch's destruction (each waits for the
+            // batch's last stream before freeing it)
+            mtgp_plan_destroy(b->eager_plan);
+            b->eager_plan = nullptr;
+            mtgp_plan_t *p = mtgp_batch_plan_create(b, reqs, nreq);
+            if (!p) {
+                const int e = mtgp_last_error();
+                return e != MTGP_OK ? e : fail(MTGP_EDEVICE);
+            }
+            b->eager_plan = p;
+            return mtgp_plan_launch(p, stream);
+        }
+    }
     finish_items(b, items, shape);
     const uint32_t nitems = (uint32_t)items.size();
     if (b->items_pending) {
@@ -1242,6 +1277,10 @@ int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     b->last = s;
     return MTGP_OK;
 }
+
+}  // namespace mtgp_impl
+
+extern "C" {
 
 int mtgp_batch_generate_plain(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream)
 {

@@ -11,6 +11,7 @@
 // order, so each request gets exactly the stream segment it would get alone,
 // and requests that arrive while others run join at the next tick.
 #include "../../include/mtgp.h"
+#include "mtgp_host.h"
 
 #include <hip/hip_runtime.h>
 
@@ -123,7 +124,7 @@ int launch_tick(mtgp_server *s)
         s->spare_events.push_back(e);
     }
     t.done = s->spare_events.back();
-    const int rc = mtgp_batch_generate(s->b, s->scratch.data(), (uint32_t)s->scratch.size(), s->stream);
+    const int rc = mtgp_impl::batch_generate(s->b, s->scratch.data(), (uint32_t)s->scratch.size(), s->stream, false);
     if (rc != MTGP_OK)
         return rc;
     if (hipEventRecord(t.done, s->stream) != hipSuccess)

@@ -574,3 +574,33 @@ def test_single_generator_split_calls(M):
         out = g.generate(100000, 1)
         np.testing.assert_array_equal(host_bits(out), O.generate(ps, st2, 100000, 1))
         g.close()
+
+
+def test_eager_batch_calls_split(M):
+    """With a split limit, an eager batch call holding a long request runs as
+    jump-ahead segments (a one-off plan, replaced by the next such call);
+    outputs equal the unsplit stream across consecutive calls, a short call
+    that stays unsplit, and every kind."""
+    import torch
+    params = I.draw_param_sets([11213] * 3, 97) + I.draw_param_sets([23209], 98)
+    seeds = I.state_seeds(len(params))
+    b = M.Batch(params, seeds)
+    b.set_split(64)
+    states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
+    calls = ((200004, (0, 1, 2, 0)), (998, (1, 0, 2, 3)), (150000, (3, 2, 1, 0)), (300002, (0, 0, 3, 0)))
+    for n, kinds in calls:
+        say(f"eager split call n={n} kinds={kinds}")
+        bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in params]
+        b.generate([(g, kinds[g], n, bufs[g]) for g in range(len(params))])
+        torch.cuda.synchronize()
+        for g in range(len(params)):
+            if kinds[g] == 3:
+                assert np.abs(host_f32(bufs[g]) - O.normals(params[g], states[g], n)).max() <= NORMAL_ATOL
+            else:
+                np.testing.assert_array_equal(host_bits(bufs[g]), O.generate(params[g], states[g], n, kinds[g]),
+                                              err_msg=f"n={n} gen={g} kind={kinds[g]}")
+    for g in range(len(params)):
+        words, consumed = b.get_state(g)
+        np.testing.assert_array_equal(words, states[g])
+        assert consumed == sum(n for n, _ in calls)
+    b.close()
