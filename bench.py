@@ -101,10 +101,20 @@ def cpu_baseline(params, n_per_gen, kinds, threads, reps=30):
         t1 = time.perf_counter()
         O.generate(ps, st, m, O.U32)
         single[f"p{mexp}"] = round(m / (time.perf_counter() - t1) / 1e6, 1)
+    # the second reading (matrix form, pure Python) on the single-stream set:
+    # a 2^16-output sample, and what the whole 2^20-output stream would take
+    from oracle import pyref as P
+    (ps1,), n1 = I.single_stream()
+    m = 1 << 16
+    t1 = time.perf_counter()
+    P.generate(ps1, list(O.seed_state(I.STATE_SEED_BASE, ps1.mexp)), m, O.U32)
+    py_s = time.perf_counter() - t1
     return {"value": round(total / dt / 1e9, 4), "unit": "G numbers/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(params)} generators x {len(kinds)} kinds x {reps} chunks of {n_per_gen} outputs "
                       f"({total} numbers, {dt:.2f} s wall on {threads} threads)",
-            "single_core_M_numbers_s": single}
+            "single_core_M_numbers_s": single,
+            "matrix_form_python": {"numbers_s": round(m / py_s, 1), "sample": f"{m} outputs of the single stream",
+                                   "single_stream_s": round(n1 / (m / py_s), 1)}}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mtgp_kernel_headline_128x4M_traffic.md")
