@@ -308,7 +308,8 @@ class Batch:
         return arr, len(reqs)
 
     def generate(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
-        """requests: iterable of (gen, kind, n, out tensor or device address)."""
+        """requests: iterable of (gen, kind, n, out tensor or device address). With a split
+        limit set, a call holding a longer request runs as jump-ahead segments."""
         arr, k = self._reqs(requests)
         _check(lib().mtgp_batch_generate(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate")
 
@@ -331,7 +332,8 @@ class Batch:
         _check(lib().mtgp_batch_generate_plain(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate_plain")
 
     def set_split(self, max_rounds: int):
-        """Split plan requests longer than max_rounds rounds into jump-ahead segments (0: off)."""
+        """Split requests longer than max_rounds rounds into jump-ahead segments (0: off), in plans
+        and in eager generate calls (such a call runs as a one-off plan)."""
         _check(lib().mtgp_batch_set_split(self._h, max_rounds), "mtgp_batch_set_split")
 
     def autotune(self, requests: Iterable, reps: int = 5, stream: Optional[torch.cuda.Stream] = None) -> dict:
