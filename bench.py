@@ -301,6 +301,8 @@ def round_width(N, M, tuning):
     W = min(N - M, lanes * s), s the largest steps per lane allowed by the
     shape with lanes * s <= N - M (the library's own rule)."""
     mode = tuning["mode"]
+    if mode >= 0 and (mode & 3) == 2:
+        return 64   # chunked form: a round is one chunk of 64 steps
     if mode < 0:
         wave, threads, cap = False, 256, 4
     else:

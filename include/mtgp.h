@@ -232,8 +232,10 @@ void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's la
  * Autotuner for a request list (unique generators, as for plans). Times `reps`
  * plan launches on `stream` for each candidate configuration -- the automatic
  * launch shape with no split and with split limits halving from the longest
- * request's round count down to 128 rounds (seven halvings, then more only
- * while each one is the fastest so far), then, at the best split limit,
+ * request's round count (rounds of the automatic shape) down to 128 rounds
+ * (seven halvings, then more only while each one is the fastest so far),
+ * then, at the best split limit, the chunked form (mode 2) with 64/256/1024
+ * lanes per workgroup and read-ahead 2 (and 256 lanes with read-ahead 1),
  * workgroup forms of 128/256/512/1024 lanes with 1-4 steps per lane and the
  * wavefront form, then the best of these with the other recursion-table
  * form (MTGP_MODE_REC_BASIS) -- and keeps the fastest (a later candidate must be at least
@@ -261,16 +263,31 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
  *           rounds; steps per lane per round up to `spl` (1, 2 or 4).
  *   mode 1: one wavefront per generator, `threads`/64 wavefronts per
  *           workgroup, no barriers; spl up to 1, 2, 4, 6, 8, 12 or 16.
+ *   mode 2: chunked form: one wavefront per generator, `threads`/64
+ *           wavefronts per workgroup, no barriers. Each wavefront takes the
+ *           steps 64 at a time (one per lane) and keeps three such chunks in
+ *           flight: the LDS reads of chunk q + spl + 1, the recursion of
+ *           chunk q + 1 up to its table lookups, and the write-back and
+ *           output of chunk q; spl (1 or 2) is the read-ahead in chunks and
+ *           needs N - M >= 64 (spl + 2) for every generator served (the
+ *           steps of a chunk then never depend on the two chunks before it,
+ *           section 3.2). The state lives in an LDS ring of lds_words words
+ *           (a power of two from 512 to 4096, at least N + 64; 0 = automatic),
+ *           each word stored twice so that no read wraps. This is the
+ *           automatic shape of a batch when every request's generator
+ *           allows it (read-ahead 2 when all allow it).
  *   mode | MTGP_MODE_REC_BASIS: the recursion table rec[u & 0xf] is evaluated
  *           from its four F2 basis words in registers instead of read from
  *           LDS: more vector instructions per step, but no lookup on the
  *           chain of a round. Which form is faster depends on the workload;
- *           the autotuner tries both.
- * Each generator uses the largest supported s <= spl with lanes*s <= N - M
- * (lanes = threads in mode 0, 64 in mode 1), so a round computes
- * W = min(N - M, lanes*s) steps (section 3.2). lds_words is the LDS window per
- * generator (0 = automatic; must be >= 2N + lanes*s for every generator
- * served) and grid the number of workgroups (0 = automatic). mode < 0
+ *           the autotuner tries both. (Modes 0 and 1; the chunked form
+ *           always looks the table up.)
+ * In modes 0 and 1 each generator uses the largest supported s <= spl with
+ * lanes*s <= N - M (lanes = threads in mode 0, 64 in mode 1), so a round
+ * computes W = min(N - M, lanes*s) steps (section 3.2); in mode 2 a round is
+ * one chunk of 64 steps (split limits count chunks). lds_words is the LDS
+ * window per generator (0 = automatic; must be >= 2N + lanes*s for every
+ * generator served) and grid the number of workgroups (0 = automatic). mode < 0
  * restores the automatic choice. Returns MTGP_EINVAL for an unsupported
  * shape; a batch call whose requests do not fit the shape fails with
  * MTGP_EINVAL.

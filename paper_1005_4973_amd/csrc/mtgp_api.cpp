@@ -130,32 +130,64 @@ bool spl_supported(int mode, int spl)
 {
     if (mode == kModeGroup)
         return spl == 1 || spl == 2 || spl == 4;
+    if (mode == kModeChunk)
+        return spl == 1 || spl == 2;
     return spl == 1 || spl == 2 || spl == 4 || spl == 6 || spl == 8 || spl == 12 || spl == 16;
 }
 
 uint32_t shape_units(const LaunchShape &s) { return s.mode == kModeGroup ? 1u : (uint32_t)(s.threads / 64); }
 
+// LDS words per wavefront of the chunked form with ring length L: the ring
+// and its copy, and the two 16-word tables.
+size_t chunk_unit_words(uint32_t L) { return 2u * (size_t)L + 32u; }
+
 // LDS bytes a launch shape asks for per workgroup.
 size_t shape_lds_bytes(const LaunchShape &s)
 {
+    if (s.mode == kModeChunk)
+        return (size_t)shape_units(s) * chunk_unit_words((uint32_t)s.lds_words) * 4u;
     return (size_t)shape_units(s) * (kUnitLdsExtra + (size_t)s.lds_words) * 4u;
 }
 
+constexpr uint32_t kChunkMaxRing = 4096;   // ring lengths the chunked kernel is built for: 512 .. 4096
+
 uint32_t max_window_words(const LaunchShape &s, size_t max_lds)
 {
+    if (s.mode == kModeChunk) {
+        uint32_t L = kChunkMaxRing;
+        while (L > 512 && shape_units(s) * chunk_unit_words(L) * 4u > max_lds)
+            L /= 2;
+        return L;
+    }
     return (uint32_t)(max_lds / 4u / shape_units(s) - kUnitLdsExtra);
 }
 
-// Window a generator needs under a shape: 2N + lanes * item_spl words.
-uint32_t window_need(const GenRecord &r, const LaunchShape &s) { return 2 * r.N + round_span(r.N, r.M, s); }
+// Whether the chunked form with read-ahead `depth` can run a generator
+// (N - M >= 64 (depth + 2), and a ring it is built for).
+bool chunk_ok(const GenRecord &r, uint32_t depth)
+{
+    return r.N - r.M >= chunk_min_gap(depth) && chunk_ring_words(r.N) <= kChunkMaxRing;
+}
+
+// Window a generator needs under a shape: 2N + lanes * item_spl words; the
+// chunked form's ring length (no length serves a generator it cannot run).
+uint32_t window_need(const GenRecord &r, const LaunchShape &s)
+{
+    if (s.mode == kModeChunk)
+        return chunk_ok(r, (uint32_t)s.spl) ? chunk_ring_words(r.N) : UINT32_MAX;
+    return 2 * r.N + round_span(r.N, r.M, s);
+}
 
 bool shape_valid(const LaunchShape &s, size_t max_lds)
 {
-    if (s.mode != kModeGroup && s.mode != kModeWave)
+    if (s.mode != kModeGroup && s.mode != kModeWave && s.mode != kModeChunk)
         return false;
     if (s.threads < 64 || s.threads > 1024 || s.threads % 64 != 0)
         return false;
     if (!spl_supported(s.mode, s.spl) || s.lds_words <= 0 || s.grid <= 0)
+        return false;
+    if (s.mode == kModeChunk && (s.lds_words < 512 || s.lds_words > (int)kChunkMaxRing ||
+                                 (s.lds_words & (s.lds_words - 1)) != 0))
         return false;
     return shape_lds_bytes(s) <= max_lds;
 }
@@ -270,6 +302,46 @@ namespace {
 // LDS and the grid is k * CUs: the hardware then has to place k workgroups on
 // every CU. (Left free, it packed several latency-bound generators onto one
 // CU while others idled.) k = 1 gives each generator a whole CU.
+// Chunked-form launch for a set of items whose generators it can all run:
+// `threads` lanes per workgroup (one item per wavefront), the least ring
+// that serves every item, and as many workgroups as the items fill, up to
+// kChunkWavesPerCu wavefronts on every CU.
+constexpr uint32_t kChunkWavesPerCu = 16;
+
+LaunchShape chunk_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, int threads = 256, int depth = 0)
+{
+    LaunchShape s;
+    s.mode = kModeChunk;
+    s.threads = threads;
+    // read two chunks ahead where every item allows it (the deeper pipeline
+    // measured 3-6 % faster), else one
+    if (depth == 0) {
+        depth = 2;
+        for (const WorkItem &it : items)
+            if (!chunk_ok(b->recs[it.gen], 2))
+                depth = 1;
+    }
+    s.spl = depth;
+    uint32_t L = 512;
+    for (const WorkItem &it : items)
+        L = std::max(L, chunk_ring_words(b->recs[it.gen].N));
+    s.lds_words = (int)L;
+    const uint32_t units = (uint32_t)threads / 64u;
+    const uint32_t by_lds = (uint32_t)(kLdsPerCu / (chunk_unit_words(L) * 4u)) / units;
+    const uint32_t per_cu = std::max(1u, std::min(by_lds, std::max(1u, kChunkWavesPerCu / units)));
+    const uint64_t want = (items.size() + units - 1) / units;
+    s.grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)per_cu * (uint64_t)b->cu_count));
+    return s;
+}
+
+bool all_chunk_ok(const mtgp_batch *b, const std::vector<WorkItem> &items, uint32_t depth = 1)
+{
+    for (const WorkItem &it : items)
+        if (!chunk_ok(b->recs[it.gen], depth))
+            return false;
+    return !items.empty();
+}
+
 LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, int threads = 256,
                                 int spl = 4)
 {
@@ -300,7 +372,11 @@ LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem>
 int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, LaunchShape &out)
 {
     LaunchShape s;
-    if (b->have_override && b->override_shape.mode == kModeGroup && b->override_shape.lds_words == 0 &&
+    if (b->have_override && b->override_shape.mode == kModeChunk && b->override_shape.lds_words == 0 &&
+        b->override_shape.grid == 0) {
+        // chunked form with automatic ring and grid
+        s = chunk_shape(b, items, b->override_shape.threads, b->override_shape.spl);
+    } else if (b->have_override && b->override_shape.mode == kModeGroup && b->override_shape.lds_words == 0 &&
         b->override_shape.grid == 0) {
         // workgroup form with automatic window and grid: placed like the default
         s = batch_default_shape(b, items, b->override_shape.threads, b->override_shape.spl);
@@ -318,6 +394,8 @@ int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, Launc
             const uint64_t want = (items.size() + units - 1) / units;
             s.grid = (int)std::min<uint64_t>(want, resident_groups(s, b->cu_count));
         }
+    } else if (all_chunk_ok(b, items)) {
+        s = chunk_shape(b, items);
     } else {
         s = batch_default_shape(b, items);
     }
@@ -1114,7 +1192,7 @@ int mtgp_set_launch(mtgp_t *g, int mode, int threads, int spl, int lds_words)
     s.threads = mode == kModeGroup ? threads : 64;
     s.spl = spl;
     s.grid = 1;
-    s.lds_words = 1;
+    s.lds_words = mode == kModeChunk ? 512 : 1;
     if (!shape_valid(s, g->max_lds) || lds_words < 0)
         return fail(MTGP_EINVAL);
     s.lds_words = lds_words > 0 ? lds_words : (int)max_window_words(s, g->max_lds);
@@ -1321,7 +1399,7 @@ int mtgp_batch_set_launch(mtgp_batch_t *b, int mode, int threads, int spl, int l
     s.mode = mode & ~kModeRecBasis;
     s.threads = threads;
     s.spl = spl;
-    s.lds_words = lds_words > 0 ? lds_words : 1;
+    s.lds_words = lds_words > 0 ? lds_words : (s.mode == kModeChunk ? 512 : 1);
     s.grid = grid > 0 ? grid : 1;
     if (lds_words < 0 || grid < 0 || !shape_valid(s, b->max_lds))
         return fail(MTGP_EINVAL);
@@ -1539,8 +1617,13 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     };
 
     // split limits: none, then halving from the longest request's rounds
+    // (rounds of the automatic shape, in which the split limits are tried)
     std::vector<WorkItem> items = items_of(reqs, nreq);
-    LaunchShape ds = batch_default_shape(b, items);
+    b->have_override = false;
+    LaunchShape ds;
+    if (resolve_shape(b, items, ds) != MTGP_OK)
+        ds = batch_default_shape(b, items);
+    b->have_override = had_override;
     uint64_t rmax = 0;
     for (const WorkItem &it : items) {
         const GenRecord &r = b->recs[it.gen];
@@ -1577,7 +1660,9 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     };
     // launch shapes at the best split limit
     const uint32_t split = best_of().split;
-    const int shapes[][3] = {{kModeGroup, 256, 1}, {kModeGroup, 256, 2}, {kModeGroup, 512, 1},
+    const int shapes[][3] = {{kModeChunk, 64, 2},  {kModeChunk, 256, 2}, {kModeChunk, 1024, 2},
+                             {kModeChunk, 256, 1},
+                             {kModeGroup, 256, 1}, {kModeGroup, 256, 2}, {kModeGroup, 512, 1},
                              {kModeGroup, 512, 2}, {kModeGroup, 1024, 1}, {kModeGroup, 128, 4},
                              {kModeWave, 256, 8}};
     for (const auto &sh : shapes) {
@@ -1590,9 +1675,11 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
         c.shape.lds_words = 0;
         c.shape.grid = 0;
         LaunchShape probe = c.shape;
-        probe.lds_words = 1;
+        probe.lds_words = sh[0] == kModeChunk ? 512 : 1;
         probe.grid = 1;
         if (!shape_valid(probe, b->max_lds))
+            continue;
+        if (sh[0] == kModeChunk && !all_chunk_ok(b, items, (uint32_t)sh[2]))
             continue;
         trial(c);
         tried.push_back(c);

@@ -111,25 +111,50 @@ static_assert(sizeof(WorkItem) == 32, "WorkItem layout");
 // Launch shape of the generation kernels.
 constexpr int kModeGroup = 0;   // one workgroup per generator, a barrier per round
 constexpr int kModeWave = 1;    // one wavefront per generator, no barriers
+constexpr int kModeChunk = 2;   // one wavefront per generator, 64-step chunks pipelined three deep
 constexpr int kModeRecBasis = 4; // flag in the public mode value: LaunchShape::rec_basis
 
+// The chunked form issues the LDS reads of a chunk of 64 steps `depth`
+// (1 or 2) iterations before it computes it, and computes it one iteration
+// before finishing it: chunk q + depth + 1 must depend only on chunks up to
+// q - 1, i.e. N - M >= 64 (depth + 2).
+inline uint32_t chunk_min_gap(uint32_t depth) { return 64u * (depth + 2u); }
+
+// Ring length of the chunked form for a state of N words: the least power of
+// two L >= max(512, N + 64) (the ring holds the N live words plus a chunk;
+// 512 keeps every block of eight chunks inside one turn of the ring).
+inline uint32_t chunk_ring_words(uint32_t N)
+{
+    uint32_t L = 512;
+    while (L < N + 64)
+        L *= 2;
+    return L;
+}
+
 struct LaunchShape {
-    int mode;        // kModeGroup or kModeWave
+    int mode;        // kModeGroup, kModeWave or kModeChunk
     int threads;     // workgroup size (multiple of 64, <= 1024)
     int spl;         // largest steps per lane per round an item may use
-                     // (group: 1, 2, 4; wave: 1, 2, 4, 6, 8, 12, 16)
-    int lds_words;   // LDS window length L in words per generator (>= 2N + lanes*spl of every item)
+                     // (group: 1, 2, 4; wave: 1, 2, 4, 6, 8, 12, 16); chunk form: the
+                     // read-ahead depth in chunks (1 or 2)
+    int lds_words;   // group and wave forms: LDS window length in words per generator
+                     // (>= 2N + lanes*spl of every item); chunk form: ring length L
+                     // (a power of two >= chunk_ring_words(N) of every item)
     int grid;        // workgroups
     int rec_basis = 0;  // 1: recursion table from its F2 basis in registers, 0: LDS lookup
+                        // (group and wave forms; the chunked form always looks it up)
 };
 
 inline uint32_t shape_lanes(const LaunchShape &s) { return s.mode == kModeGroup ? (uint32_t)s.threads : 64u; }
 
 // Steps per lane per round for a generator under a launch shape: the largest
 // supported value s <= shape.spl with lanes*s <= N - M (every slot of a round
-// useful), or 1 when even one slot per lane exceeds N - M.
+// useful), or 1 when even one slot per lane exceeds N - M. The chunked form
+// takes one step per lane per chunk (its "round" is a chunk of 64 steps).
 inline uint16_t item_spl(uint32_t N, uint32_t M, const LaunchShape &s)
 {
+    if (s.mode == kModeChunk)
+        return 1;
     static const uint16_t group_spl[] = {4, 2, 1};
     static const uint16_t wave_spl[] = {16, 12, 8, 6, 4, 2, 1};
     const uint16_t *cand = s.mode == kModeGroup ? group_spl : wave_spl;
@@ -141,9 +166,12 @@ inline uint16_t item_spl(uint32_t N, uint32_t M, const LaunchShape &s)
     return 1;
 }
 
-// W of a generator under a launch shape: min(N - M, lanes * item_spl).
+// W of a generator under a launch shape: min(N - M, lanes * item_spl); 64
+// (one chunk) in the chunked form.
 inline uint32_t round_width(uint32_t N, uint32_t M, const LaunchShape &s)
 {
+    if (s.mode == kModeChunk)
+        return 64u;
     const uint32_t w = N - M;
     const uint32_t cap = shape_lanes(s) * item_spl(N, M, s);
     return w < cap ? w : cap;

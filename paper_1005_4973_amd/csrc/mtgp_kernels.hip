@@ -426,6 +426,271 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Chunked wavefront form (kModeChunk). One wavefront runs one work item at a
+// time, with no barrier. The stream is cut into chunks of 64 consecutive
+// steps, one step per lane. Step j reads x_j, x_{j+1}, x_{j+M-1} and
+// x_{j+M}; the newest of them was written by step j - (N - M). So when
+// N - M >= 192, chunk q+2 depends only on chunks up to q-1, and the loop keeps
+// three chunks in flight: it issues the LDS reads of chunk q+2, computes chunk
+// q+1 up to its table lookups, and finishes chunk q (new word back to LDS,
+// output converted and stored). LDS operations of one wavefront complete in
+// issue order, so the reads of chunk q+3, issued after chunk q's write, see
+// it. This is section 3.2's round parallelism with the N - M independent steps
+// taken 64 at a time in a software pipeline instead of all at once behind a
+// barrier.
+//
+// The state lives in a ring of L words (L a power of two, L >= N + 64): x_p
+// sits in slot p mod L. A chunk reads slots a .. a + M with a = (64q + lane)
+// mod L, i.e. up to M - 1 slots past the ring's end, so every new word is
+// written twice, at its slot and L slots on (one two-address LDS write), and
+// the reads never wrap. No compaction copy is needed. (Writing the second
+// copy only for the chunks that need it takes a branch per chunk, after which
+// the compiler waits for every outstanding LDS operation and the pipeline
+// drains.) LDS per wavefront: 2L ring words at a multiple of 2L words, so a
+// slot's byte address is (4 slot) & (4L - 1) | ring base; after all rings,
+// each wavefront's 16-word recursion table and 16-word output table, each at
+// a multiple of 64 bytes, so a lookup's address is (4 index) | table base.
+// ---------------------------------------------------------------------------
+
+typedef __attribute__((address_space(3))) uint32_t lds_word;
+
+// HBM words through global-address-space pointers: generic (flat) accesses
+// also count on the LDS counter, and with one possibly outstanding the
+// compiler can only wait for all LDS operations
+typedef __attribute__((address_space(1))) uint32_t hbm_word;
+
+__device__ __forceinline__ uint32_t hbm_get(const uint32_t *p, uint32_t k)
+{
+    return ((const hbm_word *)p)[k];
+}
+
+__device__ __forceinline__ void hbm_put(uint32_t *p, uint32_t k, uint32_t v)
+{
+    ((hbm_word *)p)[k] = v;
+}
+
+// s_waitcnt immediate for lgkmcnt(0) with the other counters unconstrained
+// (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitLgkm0 = 0xc07f;
+
+__device__ __forceinline__ uint32_t lds_get(uint32_t byte)
+{
+    return *(lds_word *)(uintptr_t)byte;
+}
+
+__device__ __forceinline__ void lds_put(uint32_t byte, uint32_t v)
+{
+    *(lds_word *)(uintptr_t)byte = v;
+}
+
+// Words of one chunk read from the ring: x_j, x_{j+1}, x_{j+M-1}, x_{j+M}.
+struct ChunkIn {
+    uint32_t a, b, c, d;
+};
+
+// A chunk after the recursion up to the table lookups: u, rec[u & 0xf] and
+// the output-table entry of the tempering index.
+struct ChunkMid {
+    uint32_t u, r, t;
+};
+
+template <int KIND, uint32_t L, uint32_t RA, uint32_t CA>
+__device__ __forceinline__ void chunk_stream(uint32_t ringb, uint32_t rtab, uint32_t otab, uint32_t N, uint32_t M,
+                                             uint32_t sh1, uint32_t sh2, uint32_t mask, uint64_t n, gu32 *out,
+                                             uint32_t *state, const uint32_t *from, uint32_t lane)
+{
+    // 2.0 in a vector register (normal kind), so that 2 - a can read a through DPP
+    float two = 2.0f;
+    if constexpr (KIND == kKindNormal)
+        asm("v_mov_b32 %0, 2.0" : "=v"(two));
+    // the start words, each at its slot and L slots on
+    for (uint32_t k = lane; k < N; k += 64) {
+        const uint32_t v = hbm_get(from, k);
+        lds_put(ringb + 4u * k, v);
+        lds_put(ringb + 4u * (k + L), v);
+    }
+    const uint32_t rA = ringb + 4u * lane;        // slot of x_j at ring position 0
+    const uint32_t rC = rA + 4u * (M - 1u);       // slot of x_{j+M-1}
+    const uint32_t wN = 4u * (N + lane);          // 4 (slot of x_{j+N}) before the wrap
+    const float shift = (lane & 1u) ? -1.0f : -0.75f;   // normal kind: angle offsets of cos and sin lanes
+
+    auto reads = [&](uint64_t q) {
+        const uint32_t s = 4u * ((64u * (uint32_t)q) & (L - 1u));
+        ChunkIn c;
+        c.a = lds_get(rA + s);
+        c.b = lds_get(rA + s + 4u);
+        c.c = lds_get(rC + s);
+        c.d = lds_get(rC + s + 4u);
+        return c;
+    };
+    auto compute = [&](const ChunkIn &c) {
+        ChunkMid m;
+        const uint32_t a = __builtin_amdgcn_bitop3_b32(c.b, c.a, mask, (uint8_t)0x78);   // x_{j+1} ^ (x_j & mask)
+        m.u = __builtin_amdgcn_bitop3_b32(a << sh1, c.d >> sh2, a, (uint8_t)0x96);
+        m.r = lds_get(((m.u << 2) & 0x3cu) | rtab);
+        if constexpr (KIND != kKindRaw) {
+            uint32_t t = c.c ^ (c.c >> 16);
+            t ^= t >> 8;
+            m.t = lds_get(((t << 2) & 0x3cu) | otab);
+        } else {
+            m.t = 0;
+        }
+        return m;
+    };
+    auto finish = [&](uint64_t q, const ChunkMid &m, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+        const uint32_t x = m.u ^ m.r;
+        const uint32_t s = 4u * ((64u * (uint32_t)q) & (L - 1u));
+        const uint32_t w = ((wN + s) & (4u * L - 1u)) | ringb;
+        lds_put(w, x);
+        lds_put(w + 4u * L, x);
+        uint32_t o = output_word<KIND>(x, m.t);
+        if constexpr (KIND == kKindNormal)
+            o = box_muller(o, shift, two);   // steps 2i and 2i+1 are lanes 2l and 2l+1 of one chunk
+        // plain stores: for many independent output streams the store-only
+        // ceiling measured 4-6 % higher than with the nontemporal hint
+        __builtin_amdgcn_raw_buffer_store_b32(o, rs, (int)(4u * lane + off), 0, 0);
+    };
+
+    const uint64_t Q = (n + 63) / 64;
+    // no scalar load may be outstanding inside the loop: scalar loads share
+    // the LDS counter but complete out of order, and with one pending the
+    // compiler can only wait for all LDS operations instead of the oldest
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    // iteration q issues the reads of chunk q + RA, computes chunk q + CA up
+    // to its table lookups and finishes chunk q; reads wait RA - CA
+    // iterations for their data, lookups CA iterations
+    ChunkIn in[RA];
+    ChunkMid mid[CA];
+#pragma unroll
+    for (uint32_t k = 0; k < RA; k++)
+        in[k] = reads(k);
+#pragma unroll
+    for (uint32_t k = 0; k < CA; k++) {
+        mid[k] = compute(in[0]);
+#pragma unroll
+        for (uint32_t r = 0; r + 1 < RA; r++)
+            in[r] = in[r + 1];
+        in[RA - 1] = reads(RA + k);
+    }
+    auto step = [&](uint64_t q, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+        // the stages stay in this order: left to itself, the scheduler
+        // moves each chunk's computation next to its reads, and the
+        // pipeline becomes a wait for every read
+        const ChunkIn fresh = reads(q + CA + RA);
+        __builtin_amdgcn_sched_barrier(0);
+        const ChunkMid m = compute(in[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        finish(q, mid[0], rs, off);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t r = 0; r + 1 < RA; r++)
+            in[r] = in[r + 1];
+        in[RA - 1] = fresh;
+#pragma unroll
+        for (uint32_t r = 0; r + 1 < CA; r++)
+            mid[r] = mid[r + 1];
+        mid[CA - 1] = m;
+    };
+    uint64_t q = 0;
+    // blocks of eight chunks: one output window (the range check drops the
+    // stores of steps >= n), stores at immediate offsets
+    for (; q + 8 <= Q; q += 8) {
+        const __amdgpu_buffer_rsrc_t rs = out_window(out + 64 * q, (uint32_t)std::min<uint64_t>(n - 64 * q, 512));
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++)
+            step(q + j, rs, 256u * j);
+    }
+    for (; q < Q; q++)
+        step(q, out_window(out + 64 * q, (uint32_t)std::min<uint64_t>(n - 64 * q, 64)), 0);
+    // x_n .. x_{n+N-1} back to HBM (section 8: the next call continues)
+    if (state != nullptr)
+        for (uint32_t k = lane; k < N; k += 64)
+            hbm_put(state, k, lds_get(ringb + 4u * ((uint32_t)(n + k) & (L - 1u))));
+}
+
+// The chunked form's kernel: each wavefront pops work items like the wave
+// form (persistent queue, one item passed by value, or item i for unit i).
+template <uint32_t L, uint32_t RA, uint32_t CA>
+__global__ __launch_bounds__(1024) void mtgp_chunk_kernel(const GenRecord *__restrict__ recs,
+                                                          uint32_t *__restrict__ states,
+                                                          const WorkItem *__restrict__ items, uint32_t nitems,
+                                                          uint32_t *counters, WorkItem single)
+{
+    extern __shared__ uint32_t smem[];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t unit = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t units = blockDim.x >> 6;
+    // dynamic LDS starts at byte 0 in this kernel (it declares no static
+    // LDS), so ring bases are multiples of 8L bytes
+    const uint32_t base = (uint32_t)(uintptr_t)(lds_word *)smem;
+    const uint32_t ringb = base + unit * 8u * L;
+    const uint32_t rtab = base + units * 8u * L + unit * 128u;
+    const uint32_t otab = rtab + 64u;
+
+    for (uint32_t iter = 0;; ++iter) {
+        WorkItem it;
+        if (items == nullptr) {
+            if (iter > 0 || blockIdx.x > 0 || unit > 0)
+                break;
+            it = single;
+        } else if (counters == nullptr) {
+            const uint32_t w = blockIdx.x * units + unit;
+            if (iter > 0 || w >= nitems)
+                break;
+            it = items[w];
+        } else {
+            uint32_t q = 0;
+            if (lane == 0)
+                q = atomicAdd(&counters[0], 1u);
+            q = __builtin_amdgcn_readfirstlane(q);
+            if (q >= nitems)
+                break;
+            it = items[q];
+        }
+        const uint32_t gen = __builtin_amdgcn_readfirstlane(it.gen);
+        const uint32_t flags = __builtin_amdgcn_readfirstlane((uint32_t)it.kind);
+        const uint32_t kind = flags & 0xffu;
+        const GenRecord &g = recs[gen];
+        const uint32_t N = g.N, M = g.M;
+        uint32_t *slot = states + g.state_off;
+        const uint32_t *from = it.src ? reinterpret_cast<const uint32_t *>(it.src) : slot;
+        uint32_t *state = (flags & kKeepState) ? nullptr : slot;
+        if (lane < 16) {
+            lds_put(rtab + 4u * lane, g.rec[lane]);
+            lds_put(otab + 4u * lane, kind == kKindU32 ? g.tmp[lane] : g.flt[lane]);
+        }
+        gu32 *out = reinterpret_cast<gu32 *>(it.out);
+        if (kind == kKindRaw) {
+            // the start words first, then the new words
+            for (uint32_t k = lane; k < N; k += 64)
+                hbm_put(out, k, hbm_get(from, k));
+            out += N;
+        }
+#define MTGP_CHUNK(K) \
+    chunk_stream<K, L, RA, CA>(ringb, rtab, otab, N, M, g.sh1, g.sh2, g.mask, it.n, out, state, from, lane)
+        if (kind == kKindU32)
+            MTGP_CHUNK(kKindU32);
+        else if (kind == kKindF12)
+            MTGP_CHUNK(kKindF12);
+        else if (kind == kKindF01)
+            MTGP_CHUNK(kKindF01);
+        else if (kind == kKindNormal)
+            MTGP_CHUNK(kKindNormal);
+        else
+            MTGP_CHUNK(kKindRaw);
+#undef MTGP_CHUNK
+    }
+    // queue reset by the last unit to finish (as in mtgp_kernel)
+    if (items != nullptr && counters != nullptr && lane == 0) {
+        const uint32_t done = atomicAdd(&counters[1], 1u);
+        if (done == gridDim.x * units - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
 hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkItem *items, uint32_t nitems,
                            uint32_t *counters, const WorkItem &single, const LaunchShape &shape,
                            hipStream_t stream)
@@ -433,6 +698,25 @@ hipError_t launch_generate(const GenRecord *recs, uint32_t *states, const WorkIt
     const dim3 grid(shape.grid), block(shape.threads);
     const uint32_t L = (uint32_t)shape.lds_words;
     const uint32_t units = shape.mode == kModeGroup ? 1u : (uint32_t)(shape.threads / 64);
+    if (shape.mode == kModeChunk) {
+        const size_t lds_c = (size_t)(shape.threads / 64) * (2u * L + 32u) * sizeof(uint32_t);
+#define MTGP_LAUNCH_CHUNK(LL, RA, CA) \
+    hipLaunchKernelGGL((mtgp_chunk_kernel<LL, RA, CA>), grid, block, lds_c, stream, recs, states, items, nitems, \
+                       counters, single)
+#define MTGP_LAUNCH_CHUNK_L(LL) \
+    if (shape.spl == 2) MTGP_LAUNCH_CHUNK(LL, 2, 1); \
+    else MTGP_LAUNCH_CHUNK(LL, 1, 1);
+        switch (L) {
+        case 512: MTGP_LAUNCH_CHUNK_L(512); break;
+        case 1024: MTGP_LAUNCH_CHUNK_L(1024); break;
+        case 2048: MTGP_LAUNCH_CHUNK_L(2048); break;
+        case 4096: MTGP_LAUNCH_CHUNK_L(4096); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef MTGP_LAUNCH_CHUNK_L
+#undef MTGP_LAUNCH_CHUNK
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)units * (kTableWords + L) * sizeof(uint32_t);
 #define MTGP_LAUNCH(W, B) \
     hipLaunchKernelGGL((mtgp_kernel<W, B>), grid, block, lds, stream, recs, states, items, nitems, counters, single, L)
@@ -656,7 +940,15 @@ hipError_t opt_in_lds(size_t bytes)
     const void *kernels[] = {reinterpret_cast<const void *>(&mtgp_kernel<false, false>),
                              reinterpret_cast<const void *>(&mtgp_kernel<false, true>),
                              reinterpret_cast<const void *>(&mtgp_kernel<true, false>),
-                             reinterpret_cast<const void *>(&mtgp_kernel<true, true>)};
+                             reinterpret_cast<const void *>(&mtgp_kernel<true, true>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<512, 1, 1>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<512, 2, 1>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<1024, 1, 1>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<1024, 2, 1>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<2048, 1, 1>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<2048, 2, 1>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<4096, 1, 1>),
+                             reinterpret_cast<const void *>(&mtgp_chunk_kernel<4096, 2, 1>)};
     for (const void *k : kernels) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
         if (e != hipSuccess)
