@@ -1,32 +1,38 @@
 """Throughput benchmark of the MTGP HIP path on one MI355X.
 
-Headline step (`value`): the 128-generator workload -- 128 distinct
-MTGP-11213 generators (M drawn by the paper's thread-count rule), 2^22
-outputs each, generated as uint32, then float32 in [1,2), then float32 in
-[0,1): three replays of HIP-graph-captured plans (one per output kind),
-each writing 2 GiB. The batch's launch shape and jump-ahead split limit are
-autotuned once, before the timed region. A replay first computes the start
-states of each stream's segments (a raw-word prefix and the jump
-correlations), then runs the persistent generation kernel: every segment's
-state is loaded into LDS, the recursion rounds run with tempering and
-conversion, outputs leave with nontemporal stores, and each generator's end
-state is stored back.
+Headline step (`value`): the batched uneven workload -- 4096 generators with
+distinct seeded parameter sets, periods 2^11213-1, 2^23209-1, 2^44497-1 in
+ratio 2:1:1, request lengths log-uniform in [2^10, 2^24] (7.16e9 numbers,
+28.6 GB), 50 % uint32 and 25 % each float kind -- as one replay of a
+HIP-graph-captured plan. The plan's launch shape and jump-ahead split limit
+are autotuned once, before the timed region. A replay first computes the
+start states of the long requests' segments (a raw-word prefix and the jump
+correlations: the prepare phase), then runs the persistent generation
+kernel over all requests and segments: each state is loaded into LDS, the
+recursion runs with tempering and conversion, outputs leave with coalesced
+stores, and each generator's end state is stored back. `value` counts every
+number of the replay over the whole replay (both phases); `roofline` is the
+generation kernel's algorithmic bytes over its own average duration, with
+the end-to-end fraction beside it.
 
 The same JSON line also reports:
-  batched_uneven  4096 generators (2:1:1 over p = 11213, 23209, 44497),
-                  lengths log-uniform in [2^10, 2^24], mixed kinds: one
-                  graph-captured persistent launch vs one launch per request
-  large_states    256 generators at p = 23209 and at p = 44497, 2^24 uint32 each
-  normals         the headline generators, 2^22 Box-Muller normals each (float32)
-  param_search    host-side search for full-period parameter sets (p = 4423, 11213) and
-                  the dimension of equidistribution k(v), Delta of one found set
-  single_stream   one MTGP-11213 generator, 2^20 uint32 per eager call, unsplit
-                  and split into jump-ahead segments
-  serving         65536 resident MTGP-11213 states behind the library's native
-                  request loop, Poisson arrivals at a swept fraction of the
-                  measured saturation rate, log-normal sizes
-                  (median 2^16, sigma 1.5, clipped to [2^10, 2^26]):
-                  p50/p99 latency and sustained numbers/s
+  independent_128   128 MTGP-11213 generators, 2^22 outputs each as uint32,
+                    float32 [1,2) and float32 [0,1) (three tuned plans)
+  batched_plain     the headline workload as one launch per request (the
+                    paper's one block per generator, run in sequence), and
+                    the critical path of the tuned plan
+  large_states      256 generators at p = 23209 and at p = 44497, 2^24 uint32 each
+  large_states_wide_m  the p = 23209 batch with M uniform in [2, N-2]
+  normals           the 128 generators, 2^22 Box-Muller normals each (float32)
+  param_search      host-side search for full-period parameter sets (p = 4423,
+                    11213, 23209) and the dimension of equidistribution k(v),
+                    Delta of found sets
+  single_stream     one MTGP-11213 generator, 2^20 uint32 per eager call, unsplit
+                    and split into jump-ahead segments
+  serving           65536 resident MTGP-11213 states behind the library's native
+                    request loop: open-loop Poisson arrivals at swept rates,
+                    log-normal sizes (median 2^16, sigma 1.5, clipped to
+                    [2^10, 2^26]): p50/p99 latency and sustained numbers/s
 `value` is numbers/s with states and parameters resident in HBM when the
 timed region starts. The sections time a launch or replay with HIP events:
 the median of 10 after 3 untimed ones (the plain one-launch-per-request
@@ -42,8 +48,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("batched_uneven", "large_states", "large_states_wide_m", "normals", "single_stream", "serving",
-            "param_search")
+SECTIONS = ("batched_plain", "independent_128", "large_states", "large_states_wide_m", "normals", "single_stream",
+            "serving", "param_search")
 
 
 def parse():
@@ -71,27 +77,27 @@ def roof(nbytes, seconds):
     return {"GBs": round(a, 1), "frac_of_8TBs": round(a / HBM_PEAK_GBS, 4)}
 
 
-def cpu_baseline(params, n_per_gen, kinds, threads, reps=30):
-    """The oracle on the host cores: one generator and kind per task, each
-    task producing `reps` chunks of the headline's per-generator length (the
-    workload's generators, kinds and lengths, about 10 s of wall time on 16
-    cores); plus single-core rates for the three periods."""
+def cpu_baseline(params, reqs, threads, passes=8):
+    """The oracle on the host cores: the headline workload's requests (every
+    generator, its requested length and kind), `passes` times over, one
+    request per task on `threads` threads; plus single-core rates for the
+    three periods and the pure-Python matrix-form reading on a small sample."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     from paper_1005_4973_amd import inputs as I
 
-    tasks = [(g, k) for g in range(len(params)) for k in kinds]
+    states = {r.gen: O.seed_state(I.STATE_SEED_BASE + r.gen, params[r.gen].mexp) for r in reqs}
 
-    def run(task):
-        g, k = task
-        st = O.seed_state(I.STATE_SEED_BASE + g, params[g].mexp)
-        for _ in range(reps):
-            O.generate(params[g], st, n_per_gen, k)
-        return reps * n_per_gen
+    def run(r):
+        O.generate(params[r.gen], states[r.gen], r.n, r.kind)
+        return r.n
 
+    order = sorted(reqs, key=lambda r: -r.n)   # longest first, as the GPU queue
     t0 = time.perf_counter()
+    total = 0
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        total = sum(ex.map(run, tasks))
+        for _ in range(passes):
+            total += sum(ex.map(run, order))
     dt = time.perf_counter() - t0
     single = {}
     for mexp in (11213, 23209, 44497):
@@ -110,24 +116,25 @@ def cpu_baseline(params, n_per_gen, kinds, threads, reps=30):
     P.generate(ps1, list(O.seed_state(I.STATE_SEED_BASE, ps1.mexp)), m, O.U32)
     py_s = time.perf_counter() - t1
     return {"value": round(total / dt / 1e9, 4), "unit": "G numbers/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(params)} generators x {len(kinds)} kinds x {reps} chunks of {n_per_gen} outputs "
+            "sample": f"the headline workload's {len(reqs)} requests (all lengths and kinds) x {passes} passes "
                       f"({total} numbers, {dt:.2f} s wall on {threads} threads)",
             "single_core_M_numbers_s": single,
             "matrix_form_python": {"numbers_s": round(m / py_s, 1), "sample": f"{m} outputs of the single stream",
                                    "single_stream_s": round(n1 / (m / py_s), 1)}}
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mtgp_kernel_headline_128x4M_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mtgp_chunk_kernel_batched_uneven_4096_traffic.md")
+TRAFFIC_PROFILE_128 = os.path.join(ROOT, "profiles", "mtgp_chunk_kernel_independent_128x4M_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1005_4973_amd", "csrc", f) for f in ("mtgp_kernels.hip", "mtgp_internal.h")]
 
 
-def measured_traffic(tuning):
-    """HBM bytes per launch of the headline generation kernel from the committed
-    counter summary, or None when the kernel sources or the tuned configuration
+def measured_traffic(tuning, path=None):
+    """HBM bytes per launch of a generation kernel from a committed counter
+    summary, or None when the kernel sources or the tuned configuration
     differ from those the counters were taken with."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path or TRAFFIC_PROFILE).read()
     except OSError:
         return None
     h = hashlib.sha256()
@@ -137,12 +144,67 @@ def measured_traffic(tuning):
                   if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:", "tuning:")))
     if fields.get("kernel_source_sha256_16", "").split()[0:1] != [h.hexdigest()[:16]]:
         return None
-    # the split limit sets the segments whose start states the kernel reads;
-    # the launch shape changes no byte the kernel moves
+    # the split limit sets the segments whose start states the kernel reads,
+    # and the launch shape the round unit the split limit counts in
     recorded = dict(kv.split("=") for kv in fields.get("tuning", "").split())
     if recorded.get("split_rounds") != str(tuning["split_rounds"]):
         return None
+    if "mode" in recorded and "mode" in tuning and recorded["mode"] != str(tuning["mode"]):
+        return None
     return int(fields["traffic_bytes_per_launch"].strip())
+
+
+def kernel_name(tuning):
+    """The generation kernel a tuned plan launches (for the roofline line)."""
+    mode = tuning["mode"]
+    if mode >= 0 and (mode & 3) == 2:
+        return "mtgp_chunk_kernel (chunked wavefront form, read-ahead {})".format(tuning["spl"])
+    if mode < 0:
+        return "generation kernel of the automatic shape"
+    return "mtgp_kernel<{}, {}>".format("true" if mode & 1 else "false", "true" if mode & 4 else "false")
+
+
+def phase_times(torch, plan, mtgp, stream, reps, warmup):
+    """Replays of a plan as its two phases with HIP events on `stream` around
+    each: per replay (prepare ms, generate ms), after `warmup` untimed
+    replays, and the wall time of the timed replays."""
+    for _ in range(warmup):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(reps)]
+    t0 = time.perf_counter()
+    for e in ev:
+        e[0].record(stream)
+        plan.launch_phase(mtgp.PHASE_PREPARE, stream)
+        e[1].record(stream)
+        plan.launch_phase(mtgp.PHASE_GENERATE, stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [(a.elapsed_time(b), b.elapsed_time(c)) for a, b, c in ev], wall
+
+
+def median(v):
+    v = sorted(v)
+    k = len(v) // 2
+    return v[k] if len(v) % 2 else 0.5 * (v[k - 1] + v[k])
+
+
+def roofline_block(alg_bytes, gen_ms, step_ms, tuning, traffic, store_gbs=None):
+    """`roofline` object for a generation kernel: algorithmic bytes per launch
+    over its average launch time, against the 8 TB/s HBM peak; the whole
+    replay (prepare and generate) beside it."""
+    achieved = alg_bytes / (gen_ms / 1e3) / 1e9
+    blk = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_name(tuning),
+           "avg_launch_ms": round(gen_ms, 4), "alg_bytes_per_launch": alg_bytes,
+           "end_to_end": {"ms_per_replay": round(step_ms, 4),
+                          "GBs": round(alg_bytes / (step_ms / 1e3) / 1e9, 1),
+                          "frac": round(alg_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    if store_gbs:
+        blk["store_ceiling_GBs"] = round(store_gbs, 1)
+        blk["frac_of_store_ceiling"] = round(achieved / store_gbs, 4)
+    return blk
 
 
 def timed_ms(torch, fn, reps=10, warmup=3):
@@ -165,77 +227,52 @@ def timed_ms(torch, fn, reps=10, warmup=3):
 
 
 # ---------------------------------------------------------------------------
-# headline: 128 independent generators
+# headline: the batched uneven workload
 # ---------------------------------------------------------------------------
 
-def headline(args, torch, I, mtgp):
-    params, n = I.independent_128()
+def workload_bytes(params, reqs):
+    """Algorithmic bytes of one launch over these requests: 4 per output, the
+    state in and out (8N) and the 256-byte parameter record per request."""
+    return sum(4 * r.n + 8 * state_words(params[r.gen].mexp) + 256 for r in reqs)
+
+
+def headline(args, torch, I, mtgp, ctx):
+    params, reqs = I.batched_uneven()
     G = len(params)
-    kinds = (I.KIND_U32, I.KIND_F12, I.KIND_F01)
+    tot = sum(r.n for r in reqs)
     batch = mtgp.Batch(params, I.state_seeds(G))
-    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+    out = torch.empty(tot, dtype=torch.int32, device="cuda")
+    base = out.data_ptr()
     stream = torch.cuda.current_stream()
-    reqs = {k: [(g, k, n, out.data_ptr() + 4 * g * n) for g in range(G)] for k in kinds}
-    # launch shape and jump-ahead split limit, tuned on the uint32 requests
-    # (outputs are identical under every choice; states are left untouched)
-    tuning = batch.autotune(reqs[I.KIND_U32], reps=3, stream=stream)
-    log(f"autotune: {tuning}")
-    plans = [batch.plan(reqs[k]) for k in kinds]
-
-    for _ in range(args.warmup):
-        for p in plans:
-            p.launch(stream)
-    torch.cuda.synchronize()
-
-    # each launch as its two phases, with events around the generation phase:
-    # segment start states (raw prefix + jump kernels), then the persistent
-    # generation kernel, the dominant one
-    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps * len(kinds))]
-    torch.cuda.synchronize()
+    rq = [(r.gen, r.kind, r.n, base + 4 * r.offset) for r in reqs]
     t0 = time.perf_counter()
-    i = 0
-    for _ in range(args.steps):
-        for p in plans:
-            ev[i][0].record(stream)
-            p.launch_phase(mtgp.PHASE_PREPARE, stream)
-            ev[i][1].record(stream)
-            p.launch_phase(mtgp.PHASE_GENERATE, stream)
-            ev[i][2].record(stream)
-            i += 1
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    # store-only ceiling: a torch fill of the same 2 GiB buffer
-    fill_ms = timed_ms(torch, lambda: out.fill_(7))
-    store_gbs = 4 * G * n / fill_ms / 1e6
-
-    numbers_per_step = G * n * len(kinds)
-    gen_ms = [b.elapsed_time(c) for a, b, c in ev]
-    prep_ms = [a.elapsed_time(b) for a, b, c in ev]
-    avg_gen_s = sum(gen_ms) / len(gen_ms) / 1e3
-    N = 351
-    # algorithmic bytes of one launch: outputs + state in and out + parameter record
-    alg_bytes = G * (4 * n + 8 * N + 256)
-    achieved = alg_bytes / avg_gen_s / 1e9
-    for p in plans:
-        p.close()
-    batch.close()
-    del out
-    torch.cuda.empty_cache()
-    mode = tuning["mode"]
-    kernel = "mtgp_kernel<{}, {}>".format("true" if mode >= 0 and mode & 1 else "false",
-                                          "true" if mode >= 0 and mode & 4 else "false")
-    return params, n, kinds, tuning, {
-        "value": round(numbers_per_step * args.steps / dt / 1e9, 3),
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(tuning),
-                     "kernel": kernel + " (persistent generation over jump-ahead segments)",
-                     "avg_launch_ms": round(avg_gen_s * 1e3, 4),
-                     "avg_prepare_ms": round(sum(prep_ms) / len(prep_ms), 4),
-                     "alg_bytes_per_launch": alg_bytes,
-                     "store_ceiling_GBs": round(store_gbs, 1),
-                     "frac_of_store_ceiling": round(achieved / store_gbs, 4)},
+    # launch shape and jump-ahead split limit (outputs are identical under
+    # every choice; states are left untouched)
+    tuning = batch.autotune(rq, reps=2, stream=stream)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune: {tuning} in {tune_s:.1f} s")
+    plan = batch.plan(rq)
+    times, wall = phase_times(torch, plan, mtgp, stream, args.steps, args.warmup)
+    plan.close()
+    prep = sum(t[0] for t in times) / len(times)
+    gen = sum(t[1] for t in times) / len(times)
+    # store-only ceiling: a torch fill of the same output buffer
+    fill_ms = timed_ms(torch, lambda: out.fill_(7), reps=5, warmup=1)
+    alg = workload_bytes(params, reqs)
+    ctx.update(params=params, reqs=reqs, batch=batch, out=out, tuning=tuning)
+    return {
+        "value": round(tot * args.steps / wall / 1e9, 3),
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "config": {"workload": "4096 generators, exponents 11213:23209:44497 in ratio 2:1:1 (distinct seeded "
+                               "parameter sets, paper M rule), request lengths log-uniform in [2^10, 2^24], "
+                               "kinds 50% uint32 / 25% float32 [1,2) / 25% float32 [0,1); one graph-captured "
+                               "plan replay per step (jump-ahead segment states, then one persistent "
+                               "generation launch)",
+                   "generators": G, "numbers_per_step": tot, "bytes_per_step": 4 * tot,
+                   "autotuned": tuning, "autotune_s": round(tune_s, 1)},
+        "roofline": {**roofline_block(alg, gen, wall / args.steps * 1e3, tuning,
+                                      measured_traffic(tuning, TRAFFIC_PROFILE), 4 * tot / fill_ms / 1e6),
+                     "avg_prepare_ms": round(prep, 4)},
     }
 
 
@@ -243,27 +280,54 @@ def headline(args, torch, I, mtgp):
 # extra sections
 # ---------------------------------------------------------------------------
 
-def batched_uneven(torch, I, mtgp):
-    params, reqs = I.batched_uneven()
+def independent_128(torch, I, mtgp, ctx):
+    """128 MTGP-11213 generators x 2^22 outputs as uint32, float32 [1,2) and
+    float32 [0,1): one tuned plan per kind, each replayed as its two phases."""
+    params, n = I.independent_128()
     G = len(params)
-    tot = sum(r.n for r in reqs)
+    kinds = (I.KIND_U32, I.KIND_F12, I.KIND_F01)
     batch = mtgp.Batch(params, I.state_seeds(G))
-    out = torch.empty(tot, dtype=torch.int32, device="cuda")
+    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    reqs = {k: [(g, k, n, out.data_ptr() + 4 * g * n) for g in range(G)] for k in kinds}
+    tuning = batch.autotune(reqs[I.KIND_U32], reps=3, stream=stream)
+    res = {"generators": G, "mexp": 11213, "outputs_per_generator": n, "autotuned": tuning, "kinds": {}}
+    alg = G * (4 * n + 8 * 351 + 256)
+    steps = []
+    for k, name in zip(kinds, ("uint32", "float32_1to2", "float32_0to1")):
+        plan = batch.plan(reqs[k])
+        times, wall = phase_times(torch, plan, mtgp, stream, 10, 3)
+        plan.close()
+        step = median([a + b for a, b in times])
+        gen = median([b for a, b in times])
+        steps.append(step)
+        res["kinds"][name] = {"ms": round(step, 4), "G_numbers_s": round(G * n / step / 1e6, 2),
+                              "roofline": {**roofline_block(alg, gen, step, tuning,
+                                                            measured_traffic(tuning, TRAFFIC_PROFILE_128)
+                                                            if k == I.KIND_U32 else None),
+                                           "avg_prepare_ms": round(median([a for a, b in times]), 4)}}
+    res["G_numbers_s_three_kinds"] = round(3 * G * n / sum(steps) / 1e6, 2)
+    batch.close()
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def batched_plain(torch, I, mtgp, ctx):
+    """The headline workload as one launch per request on one stream (one
+    workgroup per generator, as the paper runs one block per generator), and
+    the critical path of the tuned plan: its longest segment timed alone."""
+    params, reqs, batch, out, tuning = (ctx[k] for k in ("params", "reqs", "batch", "out", "tuning"))
+    tot = sum(r.n for r in reqs)
     base = out.data_ptr()
     rq = [(r.gen, r.kind, r.n, base + 4 * r.offset) for r in reqs]
-    t0 = time.perf_counter()
-    tuning = batch.autotune(rq, reps=2)
-    tune_s = time.perf_counter() - t0
-    plan = batch.plan(rq)
-    ms_b = timed_ms(torch, lambda: plan.launch())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.generate_plain(rq)
     torch.cuda.synchronize()
     ms_p = (time.perf_counter() - t0) * 1e3
-    plan.close()
-    # critical path: the segment with the most rounds under the tuned shape and
-    # split limit, timed alone (same shape, no split, one workgroup)
+    # critical path: the segment with the most rounds under the tuned shape
+    # and split limit, timed alone (same shape, no split)
     r_max, crit = 0, None
     for r in reqs:
         ps = params[r.gen]
@@ -273,23 +337,20 @@ def batched_uneven(torch, I, mtgp):
         J = -(-r.n // S)
         if -(-J // W) > r_max:
             r_max, crit = -(-J // W), (r, J)
+    split = tuning["split_rounds"]
     batch.set_split(0)
     (r, J) = crit
     p1 = batch.plan([(r.gen, r.kind, J, base + 4 * r.offset)])
     ms_c = timed_ms(torch, lambda: p1.launch())
     p1.close()
-    batch.close()
-    del out
-    torch.cuda.empty_cache()
-    Ns = {11213: 351, 23209: 726, 44497: 1391}
-    alg = sum(4 * r.n + 8 * Ns[params[r.gen].mexp] + 256 for r in reqs)
-    return {"generators": G, "numbers": tot,
-            "batched": {"ms": round(ms_b, 3), "G_numbers_s": round(tot / ms_b / 1e6, 2), **roof(alg, ms_b / 1e3),
-                        "autotuned": tuning, "autotune_s": round(tune_s, 1)},
-            "critical_path": {"segment_rounds": r_max, "mexp": params[crit[0].gen].mexp, "segment_outputs": crit[1],
-                              "alone_ms": round(ms_c, 3), "makespan_over_bound": round(ms_b / ms_c, 2)},
+    batch.set_split(split)
+    head_ms = ctx.get("head_ms")
+    return {"numbers": tot,
             "plain_one_launch_per_request": {"ms": round(ms_p, 1), "G_numbers_s": round(tot / ms_p / 1e6, 3)},
-            "speedup_batched_vs_plain": round(ms_p / ms_b, 1)}
+            "speedup_batched_vs_plain": round(ms_p / head_ms, 1) if head_ms else None,
+            "critical_path": {"segment_rounds": r_max, "mexp": params[crit[0].gen].mexp, "segment_outputs": crit[1],
+                              "alone_ms": round(ms_c, 3),
+                              "makespan_over_bound": round(head_ms / ms_c, 2) if head_ms else None}}
 
 
 def state_words(mexp):
@@ -313,8 +374,9 @@ def round_width(N, M, tuning):
     return min(N - M, lanes * s)
 
 
-def large_states(torch, I, mtgp):
+def large_states(torch, I, mtgp, ctx):
     res = {}
+    stream = torch.cuda.current_stream()
     for mexp, N in ((23209, 726), (44497, 1391)):
         params, n = I.large_states(mexp)
         G = len(params)
@@ -322,22 +384,26 @@ def large_states(torch, I, mtgp):
         out = torch.empty(G * n, dtype=torch.int32, device="cuda")
         rq = [(g, 0, n, out.data_ptr() + 4 * g * n) for g in range(G)]
         t0 = time.perf_counter()
-        tuning = batch.autotune(rq, reps=2)
+        tuning = batch.autotune(rq, reps=2, stream=stream)
         tune_s = time.perf_counter() - t0
         plan = batch.plan(rq)
-        ms = timed_ms(torch, lambda: plan.launch())
+        times, wall = phase_times(torch, plan, mtgp, stream, 10, 3)
         plan.close()
         batch.close()
         del out
         torch.cuda.empty_cache()
+        step = median([a + b for a, b in times])
+        gen = median([b for a, b in times])
         alg = G * (4 * n + 8 * N + 256)
-        res[f"p{mexp}"] = {"generators": G, "numbers": G * n, "ms": round(ms, 3),
-                           "G_numbers_s": round(G * n / ms / 1e6, 2), **roof(alg, ms / 1e3),
+        res[f"p{mexp}"] = {"generators": G, "numbers": G * n, "ms": round(step, 3),
+                           "G_numbers_s": round(G * n / step / 1e6, 2), **roof(alg, step / 1e3),
+                           "roofline": {**roofline_block(alg, gen, step, tuning, None),
+                                        "avg_prepare_ms": round(median([a for a, b in times]), 4)},
                            "autotuned": tuning, "autotune_s": round(tune_s, 1)}
     return res
 
 
-def large_states_wide_m(torch, I, mtgp):
+def large_states_wide_m(torch, I, mtgp, ctx):
     """Sensitivity of the large-state batch to the M rule: 256 MTGP-23209
     generators x 2^24 with M uniform in [2, N-2]. The generators with small
     N - M have millions of dependent rounds; the tuned plan splits them into
@@ -368,7 +434,7 @@ def large_states_wide_m(torch, I, mtgp):
             "autotuned": tuning, "autotune_s": round(tune_s, 1)}
 
 
-def normals(torch, I, mtgp):
+def normals(torch, I, mtgp, ctx):
     """128 MTGP-11213 generators x 2^22 Gaussian deviates (Box-Muller on pairs of
     float [1,2) outputs), one tuned split plan replayed."""
     params, n = I.independent_128()
@@ -388,7 +454,7 @@ def normals(torch, I, mtgp):
             **roof(alg, ms / 1e3), "autotuned": tuning}
 
 
-def param_search(torch, I, mtgp):
+def param_search(torch, I, mtgp, ctx):
     """Host-side recursion-parameter search (section 5): full-period sets with
     an ID embedded, seeded so the draw counts are fixed; the paper's own
     search took 338 s per MTGP-11213 set on average (context only)."""
@@ -410,7 +476,7 @@ def param_search(torch, I, mtgp):
     return {"threads": threads, "runs": runs, "equidistribution": equi}
 
 
-def single_stream(torch, I, mtgp):
+def single_stream(torch, I, mtgp, ctx):
     """One generator, 2^20 uint32 per eager call: as one workgroup (the
     recursion's rounds in sequence), and split into jump-ahead segments (the
     first split call finds the orbit's annihilator and the jump polynomials;
@@ -431,7 +497,7 @@ def single_stream(torch, I, mtgp):
                                 "first_call_s": round(first_s, 3)}}
 
 
-def serving(torch, I, mtgp):
+def serving(torch, I, mtgp, ctx):
     """65536 resident MTGP-11213 states served by the library's request loop
     (mtgp_server_*, native admission and tick building; Python only feeds
     arrivals): saturation rate with all requests available at once, then
@@ -492,7 +558,9 @@ def main():
     from paper_1005_4973_amd import mtgp
 
     torch.cuda.set_device(0)
-    params, n, kinds, tuning, head = headline(args, torch, I, mtgp)
+    ctx = {}
+    head = headline(args, torch, I, mtgp, ctx)
+    ctx["head_ms"] = head["ms_per_step"]
     log(f"headline: {head['value']} G numbers/s")
 
     res = {
@@ -509,29 +577,36 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic (seeded parameter sets and states)",
-        "config": {"workload": "128 independent MTGP-11213 generators (distinct seeded parameter sets, "
-                               "M in [2,95]), 2^22 outputs each as uint32, float32 [1,2) and float32 [0,1); "
-                               "one graph-captured plan per output kind (jump-ahead segment states, then "
-                               "persistent generation)",
-                   "generators": 128, "mexp": 11213, "outputs_per_generator": n,
-                   "kinds": ["uint32", "float32_1to2", "float32_0to1"], "autotuned": tuning},
+        "config": head["config"],
         "roofline": head["roofline"],
     }
     if not args.no_cpu_baseline:
+        # 16 threads: the host CPU share of one GPU on the benchmark machine
+        # (the machine's own count is larger but shared among its GPUs)
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
-        res["cpu_baseline"] = cpu_baseline(params, n, kinds, threads)
+        res["cpu_baseline"] = cpu_baseline(ctx["params"], ctx["reqs"], threads)
         log(f"cpu baseline: {res['cpu_baseline']['value']} G numbers/s")
     sections = [s for s in args.sections.split(",") if s]
-    fns = {"batched_uneven": batched_uneven, "large_states": large_states,
+    fns = {"batched_plain": batched_plain, "independent_128": independent_128, "large_states": large_states,
            "large_states_wide_m": large_states_wide_m, "normals": normals,
            "single_stream": single_stream, "serving": serving, "param_search": param_search}
     unknown = [name for name in sections if name not in fns]
     if unknown:
         raise SystemExit(f"unknown sections: {unknown}")
+    def release_headline():
+        # the headline's batch and 28.6 GB output buffer serve batched_plain only
+        if "batch" in ctx:
+            ctx.pop("batch").close()
+            ctx.pop("out", None)
+            torch.cuda.empty_cache()
+
     for name in sections:
+        if name != "batched_plain":
+            release_headline()
         t0 = time.perf_counter()
-        res[name] = fns[name](torch, I, mtgp)
+        res[name] = fns[name](torch, I, mtgp, ctx)
         log(f"{name}: done in {time.perf_counter() - t0:.1f} s: {json.dumps(res[name])[:300]}")
+    release_headline()
     print(json.dumps(res), flush=True)
 
 

@@ -234,10 +234,12 @@ void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's la
  * launch shape with no split and with split limits halving from the longest
  * request's round count (rounds of the automatic shape) down to 128 rounds
  * (seven halvings, then more only while each one is the fastest so far),
- * then, at the best split limit, the chunked form (mode 2) with 64/256/1024
- * lanes per workgroup and read-ahead 2 (and 256 lanes with read-ahead 1),
- * workgroup forms of 128/256/512/1024 lanes with 1-4 steps per lane and the
- * wavefront form, then the best of these with the other recursion-table
+ * then the chunked form (mode 2) with 64/256/1024 lanes per workgroup and
+ * read-ahead 2 (and 256 lanes with read-ahead 1), workgroup forms of
+ * 128/256/512/1024 lanes with 1-4 steps per lane and the wavefront form, each
+ * at the split limit that cuts the same segment lengths as the best one so
+ * far (split limits count rounds of the shape in use) and at half of it,
+ * then the best of these with the other recursion-table
  * form (MTGP_MODE_REC_BASIS) -- and keeps the fastest (a later candidate must be at least
  * 2 % faster than the one it replaces) as the batch's launch shape
  * (mtgp_batch_set_launch) and split limit (mtgp_batch_set_split). Outputs are
@@ -274,8 +276,10 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
  *           section 3.2). The state lives in an LDS ring of lds_words words
  *           (a power of two from 512 to 4096, at least N + 64; 0 = automatic),
  *           each word stored twice so that no read wraps. This is the
- *           automatic shape of a batch when every request's generator
- *           allows it (read-ahead 2 when all allow it).
+ *           automatic shape of a batch call with at least 8 requests (or
+ *           jump-ahead segments) per compute unit whose generators all
+ *           allow it (read-ahead 2 when all allow it); with fewer, the
+ *           workgroup form gives each request more lanes.
  *   mode | MTGP_MODE_REC_BASIS: the recursion table rec[u & 0xf] is evaluated
  *           from its four F2 basis words in registers instead of read from
  *           LDS: more vector instructions per step, but no lookup on the

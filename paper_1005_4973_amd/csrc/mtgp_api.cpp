@@ -307,6 +307,12 @@ namespace {
 // that serves every item, and as many workgroups as the items fill, up to
 // kChunkWavesPerCu wavefronts on every CU.
 constexpr uint32_t kChunkWavesPerCu = 16;
+// The automatic shape is the chunked form only with at least this many items
+// per CU: one wavefront per item needs about eight per CU to keep a CU's
+// issue, LDS and stores busy, while with fewer items the workgroup form (four
+// wavefronts per item) both fills the GPU and gives each item a shorter
+// latency (request-loop ticks, a few hundred generators).
+constexpr uint32_t kChunkMinItemsPerCu = 8;
 
 LaunchShape chunk_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, int threads = 256, int depth = 0)
 {
@@ -394,7 +400,7 @@ int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, Launc
             const uint64_t want = (items.size() + units - 1) / units;
             s.grid = (int)std::min<uint64_t>(want, resident_groups(s, b->cu_count));
         }
-    } else if (all_chunk_ok(b, items)) {
+    } else if (all_chunk_ok(b, items) && items.size() >= (size_t)kChunkMinItemsPerCu * (size_t)b->cu_count) {
         s = chunk_shape(b, items);
     } else {
         s = batch_default_shape(b, items);
@@ -1658,8 +1664,22 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
                 k = i;
         return tried[k];
     };
-    // launch shapes at the best split limit
+    // launch shapes, each at the split limit that cuts the same segment
+    // lengths in steps as the best one so far (a split limit counts rounds,
+    // and a round's width depends on the shape), and at half of it
     const uint32_t split = best_of().split;
+    // mean round width of the request list under a shape, weighted by rounds
+    auto mean_width = [&](const LaunchShape &s) {
+        uint64_t steps = 0, rounds = 0;
+        for (const WorkItem &it : items) {
+            const GenRecord &r = b->recs[it.gen];
+            const uint64_t w = round_width(r.N, r.M, s);
+            steps += it.n;
+            rounds += (it.n + w - 1) / w;
+        }
+        return rounds ? (double)steps / (double)rounds : 1.0;
+    };
+    const double w_auto = mean_width(ds);
     const int shapes[][3] = {{kModeChunk, 64, 2},  {kModeChunk, 256, 2}, {kModeChunk, 1024, 2},
                              {kModeChunk, 256, 1},
                              {kModeGroup, 256, 1}, {kModeGroup, 256, 2}, {kModeGroup, 512, 1},
@@ -1681,8 +1701,15 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
             continue;
         if (sh[0] == kModeChunk && !all_chunk_ok(b, items, (uint32_t)sh[2]))
             continue;
-        trial(c);
-        tried.push_back(c);
+        const uint32_t eq = split == 0 ? 0u
+                                       : (uint32_t)std::max(128.0, (double)split * w_auto / mean_width(c.shape));
+        for (uint32_t sp : {eq, eq / 2}) {
+            if (!device_ok || (sp == eq / 2 && (eq == 0 || sp < 128)))
+                continue;
+            c.split = sp;
+            trial(c);
+            tried.push_back(c);
+        }
     }
     // the best so far with the other recursion-table form (the automatic
     // shape is the 256-lane workgroup form with up to 4 steps per lane)

@@ -3,17 +3,19 @@
 Runs, in order:
   1. a device-to-device copy of exactly 1 GiB (torch), whose FETCH_SIZE and
      WRITE_SIZE readings calibrate the counters (1 GiB read, 1 GiB written);
-  2. the headline workload as bench.py times it: 128 MTGP-11213 generators
-     (paper M rule), 2^22 uint32 outputs each; the batch is autotuned on
-     these requests (the chosen configuration is printed), or set to the
-     configuration given with --split and --shape, then the plan is replayed
-     three times as its two phases (prepare: raw prefix and jump kernels;
-     generate: the persistent generation kernel). Counters of the last replay
-     are the ones to read.
+  2. one workload as bench.py times it, in a given configuration (split
+     limit and launch shape) or autotuned on its requests (the chosen
+     configuration is printed); the plan is replayed three times as its two
+     phases (prepare: raw prefix and jump kernels; generate: the persistent
+     generation kernel). Counters of the last replay are the ones to read.
+     Workloads:
+       batched_uneven   4096 generators (11213:23209:44497 = 2:1:1), lengths
+                        log-uniform in [2^10, 2^24], mixed kinds (the headline)
+       independent_128  128 MTGP-11213 generators, 2^22 uint32 outputs each
 
-Example (the configuration bench.py's autotuner picks for this workload):
+Example (the configuration bench.py's autotuner picks for the headline):
   rocprofv3 --pmc FETCH_SIZE -d out -o fetch --output-format csv -- \
-      python paper_1005_4973_amd/profile_workload.py --split 2048 --shape auto
+      python paper_1005_4973_amd/profile_workload.py --workload batched_uneven --split 32768 --shape 2,256,2
 """
 import os
 import sys
@@ -27,6 +29,7 @@ COPY_BYTES = 1 << 30
 def main():
     import argparse
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="batched_uneven", choices=("batched_uneven", "independent_128"))
     ap.add_argument("--split", type=int, default=None, help="split limit in rounds (default: autotune)")
     ap.add_argument("--shape", default="auto", help="'auto' or mode,threads,spl (with --split)")
     args = ap.parse_args()
@@ -42,20 +45,27 @@ def main():
     torch.cuda.synchronize()
     del src, dst
 
-    params, n = I.independent_128()
-    G = len(params)
+    if args.workload == "batched_uneven":
+        params, reqs = I.batched_uneven()
+        G = len(params)
+        tot = sum(r.n for r in reqs)
+        out = torch.empty(tot, dtype=torch.int32, device="cuda")
+        rq = [(r.gen, r.kind, r.n, out.data_ptr() + 4 * r.offset) for r in reqs]
+    else:
+        params, n = I.independent_128()
+        G = len(params)
+        out = torch.empty(G * n, dtype=torch.int32, device="cuda")
+        rq = [(g, I.KIND_U32, n, out.data_ptr() + 4 * g * n) for g in range(G)]
     batch = mtgp.Batch(params, I.state_seeds(G))
-    out = torch.empty(G * n, dtype=torch.int32, device="cuda")
-    reqs = [(g, I.KIND_U32, n, out.data_ptr() + 4 * g * n) for g in range(G)]
     if args.split is None:
-        print(f"autotune: {batch.autotune(reqs, reps=3)}", flush=True)
+        print(f"autotune: {batch.autotune(rq, reps=2)}", flush=True)
     else:
         batch.set_split(args.split)
         if args.shape != "auto":
             mode, threads, spl = (int(v) for v in args.shape.split(","))
             batch.set_launch(mode, threads, spl, 0, 0)
-        print(f"configuration: split {args.split}, shape {args.shape}", flush=True)
-    plan = batch.plan(reqs)
+        print(f"configuration: workload {args.workload}, split {args.split}, shape {args.shape}", flush=True)
+    plan = batch.plan(rq)
     for _ in range(3):
         plan.launch_phase(mtgp.PHASE_PREPARE)
         plan.launch_phase(mtgp.PHASE_GENERATE)

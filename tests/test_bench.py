@@ -31,6 +31,8 @@ def bench():
     (351, 78, {"mode": 4, "threads": 512, "spl": 1}, 273),      # 512 lanes: W = N - M
     (351, 78, {"mode": 1, "threads": 256, "spl": 8}, 256),      # wavefront form: 64 x 4
     (1391, 2, {"mode": 5, "threads": 256, "spl": 16}, 1024),    # 64 x 16, basis flag ignored
+    (351, 78, {"mode": 2, "threads": 256, "spl": 2}, 64),       # chunked form: a round is a chunk
+    (1391, 300, {"mode": 2, "threads": 64, "spl": 1}, 64),
 ])
 def test_round_width(bench, N, M, tuning, W):
     assert bench.round_width(N, M, tuning) == W
@@ -55,3 +57,24 @@ def test_traffic_reported_only_for_matching_sources_and_split(bench, tmp_path, m
     assert bench.measured_traffic({"split_rounds": 2048}) is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic({"split_rounds": 2048}) is None
+
+
+def test_traffic_needs_matching_launch_mode(bench, tmp_path):
+    """A counter run taken under one launch mode does not stand for another:
+    the round unit the split limit counts in depends on it."""
+    h = hashlib.sha256()
+    for f in bench.KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    p = tmp_path / "prof.md"
+    p.write_text(f"kernel_source_sha256_16: {h.hexdigest()[:16]}\n"
+                 f"tuning: split_rounds=4096 mode=2 threads=256 spl=2\ntraffic_bytes_per_launch: 99\n")
+    assert bench.measured_traffic({"split_rounds": 4096, "mode": 2}, str(p)) == 99
+    assert bench.measured_traffic({"split_rounds": 4096, "mode": 0}, str(p)) is None
+
+
+def test_roofline_block_fractions(bench):
+    blk = bench.roofline_block(8_000_000_000, 2.0, 2.5, {"mode": 2, "threads": 256, "spl": 2}, None, 6000.0)
+    assert blk["achieved"] == 4000.0 and blk["frac"] == 0.5
+    assert blk["end_to_end"]["frac"] == 0.4
+    assert blk["frac_of_store_ceiling"] == round(4000.0 / 6000.0, 4)
+    assert "chunk" in blk["kernel"]
