@@ -173,6 +173,26 @@ mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds,
 int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream);
 
 /*
+ * For callers that cannot allocate -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation: the same call as
+ * mtgp_batch_generate without jump-ahead segments (a split limit is
+ * ignored), making no device or host allocation. Its work items (at most
+ * MTGP_STATIC_MAX_ITEMS requests with n > 0) and queue counters live in a
+ * fixed array of MTGP_STATIC_SCRATCH_BYTES in this library's device code, one
+ * copy per GPU held until the process ends; the batch's pinned staging for
+ * the items is made by mtgp_batch_create. Every call on one GPU uses that
+ * GPU's copy, so calls that overlap on a GPU (other streams, other batches,
+ * other threads) race and must be serialised by the caller; calls on one
+ * stream are ordered. A call waits on the host until the previous such
+ * call of this batch has uploaded its items. Returns MTGP_EINVAL for
+ * nreq > MTGP_STATIC_MAX_ITEMS and as mtgp_batch_generate does, and
+ * MTGP_EDEVICE on a HIP error.
+ */
+#define MTGP_STATIC_MAX_ITEMS 4096
+#define MTGP_STATIC_SCRATCH_BYTES (256 + 32 * MTGP_STATIC_MAX_ITEMS)
+int mtgp_batch_generate_static(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream);
+
+/*
  * Same work as mtgp_batch_generate, but as one launch per request on
  * `stream` (the plain form, for comparison).
  */

@@ -8,6 +8,8 @@
 #include "mtgp_host.h"
 
 static_assert(mtgp_impl::kModeRecBasis == MTGP_MODE_REC_BASIS, "launch mode flag");
+static_assert(mtgp_impl::kStaticMaxItems == MTGP_STATIC_MAX_ITEMS, "allocation-free call: item limit");
+static_assert(mtgp_impl::kStaticScratchBytes == MTGP_STATIC_SCRATCH_BYTES, "allocation-free call: scratch size");
 
 #include <hip/hip_runtime.h>
 
@@ -270,6 +272,12 @@ struct mtgp_batch {
     std::vector<f2::Poly> psi;                 // annihilator of the generator's orbit (empty: none)
     std::vector<uint64_t> psi_epoch;           // epoch + 1 when psi was computed, 0 if never
     mtgp_plan *eager_plan = nullptr;           // the last eager call run as a one-off split plan
+    // allocation-free calls (mtgp_batch_generate_static): pinned staging of
+    // kStaticMaxItems items, made with the batch, and the event after which
+    // the last such call's upload has read it
+    WorkItem *h_static = nullptr;
+    hipEvent_t static_free = nullptr;
+    bool static_pending = false;
 };
 
 struct mtgp_plan {
@@ -302,6 +310,19 @@ namespace {
 // LDS and the grid is k * CUs: the hardware then has to place k workgroups on
 // every CU. (Left free, it packed several latency-bound generators onto one
 // CU while others idled.) k = 1 gives each generator a whole CU.
+// A read-only view of a work-item list (a vector, or the allocation-free
+// call's staging array): shape choices take this so that no list is copied.
+struct Items {
+    const WorkItem *ptr = nullptr;
+    size_t count = 0;
+    Items(const std::vector<WorkItem> &v) : ptr(v.data()), count(v.size()) {}
+    Items(const WorkItem *p, size_t n) : ptr(p), count(n) {}
+    const WorkItem *begin() const { return ptr; }
+    const WorkItem *end() const { return ptr + count; }
+    size_t size() const { return count; }
+    bool empty() const { return count == 0; }
+};
+
 // Chunked-form launch for a set of items whose generators it can all run:
 // `threads` lanes per workgroup (one item per wavefront), the least ring
 // that serves every item, and as many workgroups as the items fill, up to
@@ -314,7 +335,7 @@ constexpr uint32_t kChunkWavesPerCu = 16;
 // latency (request-loop ticks, a few hundred generators).
 constexpr uint32_t kChunkMinItemsPerCu = 8;
 
-LaunchShape chunk_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, int threads = 256, int depth = 0)
+LaunchShape chunk_shape(const mtgp_batch *b, Items items, int threads = 256, int depth = 0)
 {
     LaunchShape s;
     s.mode = kModeChunk;
@@ -340,7 +361,7 @@ LaunchShape chunk_shape(const mtgp_batch *b, const std::vector<WorkItem> &items,
     return s;
 }
 
-bool all_chunk_ok(const mtgp_batch *b, const std::vector<WorkItem> &items, uint32_t depth = 1)
+bool all_chunk_ok(const mtgp_batch *b, Items items, uint32_t depth = 1)
 {
     for (const WorkItem &it : items)
         if (!chunk_ok(b->recs[it.gen], depth))
@@ -348,7 +369,7 @@ bool all_chunk_ok(const mtgp_batch *b, const std::vector<WorkItem> &items, uint3
     return !items.empty();
 }
 
-LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, int threads = 256,
+LaunchShape batch_default_shape(const mtgp_batch *b, Items items, int threads = 256,
                                 int spl = 4)
 {
     LaunchShape s;
@@ -375,7 +396,7 @@ LaunchShape batch_default_shape(const mtgp_batch *b, const std::vector<WorkItem>
 
 // Resolve the launch shape for a set of items: override (with automatic
 // window and grid filled in) or default; validated against every item.
-int resolve_shape(const mtgp_batch *b, const std::vector<WorkItem> &items, LaunchShape &out)
+int resolve_shape(const mtgp_batch *b, Items items, LaunchShape &out)
 {
     LaunchShape s;
     if (b->have_override && b->override_shape.mode == kModeChunk && b->override_shape.lds_words == 0 &&
@@ -482,6 +503,10 @@ void batch_free(mtgp_batch *b)
         (void)hipHostFree(b->h_items);
     if (b->items_free)
         (void)hipEventDestroy(b->items_free);
+    if (b->h_static)
+        (void)hipHostFree(b->h_static);
+    if (b->static_free)
+        (void)hipEventDestroy(b->static_free);
     delete b;
 }
 
@@ -1264,9 +1289,16 @@ mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds,
     if (hipMemcpy(b->d_recs, b->recs.data(), count * sizeof(GenRecord), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_states, words.data(), off * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(b->d_counters, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
-        hipEventCreateWithFlags(&b->items_free, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->items_free, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->static_free, hipEventDisableTiming) != hipSuccess) {
         batch_free(b);
         fail(MTGP_EDEVICE);
+        return nullptr;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->h_static), kStaticMaxItems * sizeof(WorkItem),
+                      hipHostMallocDefault) != hipSuccess) {
+        batch_free(b);
+        fail(MTGP_ENOMEM);
         return nullptr;
     }
     return b;
@@ -1287,6 +1319,78 @@ void mtgp_batch_destroy(mtgp_batch_t *b)
 int mtgp_batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream)
 {
     return mtgp_impl::batch_generate(b, reqs, nreq, stream, true);
+}
+
+// The eager batch call without jump-ahead and without any allocation: the
+// work items are built in the batch's pinned staging array, checked and
+// ordered in place (std::sort, which needs no buffer), uploaded to this
+// GPU's fixed scratch array, whose queue counters a one-wavefront kernel
+// zeroes first; the generation kernels are the ones mtgp_batch_generate uses.
+int mtgp_batch_generate_static(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream)
+{
+    if (!b || (nreq > 0 && !reqs) || nreq > kStaticMaxItems)
+        return fail(MTGP_EINVAL);
+    if (validate_requests(b, reqs, nreq, false) != MTGP_OK)
+        return fail(MTGP_EINVAL);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *scr = nullptr;
+    if (static_scratch(&scr) != hipSuccess)
+        return fail(MTGP_EDEVICE);
+    // the previous call's upload must have read the staging array
+    if (b->static_pending) {
+        if (hipEventSynchronize(b->static_free) != hipSuccess)
+            return fail(MTGP_EDEVICE);
+        b->static_pending = false;
+    }
+    WorkItem *h = b->h_static;
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < nreq; i++) {
+        if (reqs[i].n == 0)
+            continue;
+        WorkItem &it = h[k++];
+        std::memset(&it, 0, sizeof(it));
+        it.out = reinterpret_cast<uint64_t>(reqs[i].out);
+        it.n = reqs[i].n;
+        it.gen = reqs[i].gen;
+        it.kind = (uint16_t)reqs[i].kind;
+    }
+    if (k == 0)
+        return MTGP_OK;
+    // one request per generator
+    std::sort(h, h + k, [](const WorkItem &x, const WorkItem &y) { return x.gen < y.gen; });
+    for (uint32_t j = 1; j < k; j++)
+        if (h[j].gen == h[j - 1].gen)
+            return fail(MTGP_EINVAL);
+    LaunchShape shape;
+    if (resolve_shape(b, Items(h, k), shape) != MTGP_OK)
+        return fail(MTGP_EINVAL);
+    // steps per lane, then longest critical path first (ties by generator)
+    for (uint32_t j = 0; j < k; j++)
+        h[j].spl = item_spl(b->recs[h[j].gen].N, b->recs[h[j].gen].M, shape);
+    auto cost = [&](const WorkItem &it) {
+        const GenRecord &r = b->recs[it.gen];
+        const uint64_t w = round_width(r.N, r.M, shape);
+        return (it.n + w - 1) / w * (uint64_t)it.spl;
+    };
+    std::sort(h, h + k, [&](const WorkItem &x, const WorkItem &y) {
+        const uint64_t cx = cost(x), cy = cost(y);
+        return cx != cy ? cx > cy : x.gen < y.gen;
+    });
+    uint32_t *counters = static_cast<uint32_t *>(scr);
+    WorkItem *d_items = reinterpret_cast<WorkItem *>(static_cast<char *>(scr) + kStaticCounterBytes);
+    WorkItem none;
+    std::memset(&none, 0, sizeof(none));
+    if (launch_zero_words(counters, 2, s) != hipSuccess ||
+        hipMemcpyAsync(d_items, h, (size_t)k * sizeof(WorkItem), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(b->static_free, s) != hipSuccess)
+        return fail(MTGP_EDEVICE);
+    b->static_pending = true;
+    if (launch_generate(b->d_recs, b->d_states, d_items, k, counters, none, shape, s) != hipSuccess)
+        return fail(MTGP_EDEVICE);
+    for (uint32_t j = 0; j < k; j++)
+        b->consumed[h[j].gen] += h[j].n;
+    b->last = s;
+    return MTGP_OK;
 }
 
 }  // extern "C"

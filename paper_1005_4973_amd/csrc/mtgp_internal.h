@@ -199,4 +199,17 @@ hipError_t launch_jumps(const JumpItem *d_items, const JumpItem *h_items, uint32
 // Allow every generation kernel to use up to `bytes` of dynamic LDS.
 hipError_t opt_in_lds(size_t bytes);
 
+// The allocation-free batch call's fixed device scratch: 256 bytes of queue
+// counters, then up to kStaticMaxItems work items (128 KiB + 256 bytes).
+constexpr uint32_t kStaticMaxItems = 4096;
+constexpr size_t kStaticCounterBytes = 256;
+constexpr size_t kStaticScratchBytes = kStaticCounterBytes + (size_t)kStaticMaxItems * sizeof(WorkItem);
+
+// Device address of that scratch on the current device (looked up once per
+// device, then cached).
+hipError_t static_scratch(void **ptr);
+
+// Zero n words at p with a one-wavefront kernel on `stream`.
+hipError_t launch_zero_words(uint32_t *p, uint32_t n, hipStream_t stream);
+
 }  // namespace mtgp_impl

@@ -41,6 +41,8 @@
 //                (evaluated with the hardware log2, sqrt and sine)
 #include "mtgp_internal.h"
 
+#include <mutex>
+
 namespace mtgp_impl {
 
 // LDS layout: [0,16) recursion table, [16,32) output table, [32] queue slot,
@@ -932,6 +934,53 @@ hipError_t launch_jumps(const JumpItem *d_items, const JumpItem *h_items, uint32
         k = e;
     }
     return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free batch call
+// (mtgp_batch_generate_static): the queue counters in its first 256 bytes,
+// then up to kStaticMaxItems work items. One copy per GPU, for the life of
+// the process; every such call on a GPU uses that GPU's copy.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        // the symbol's address on this device (host code must not pass the
+        // array's name itself to a kernel: it stands for no device address)
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+__global__ void mtgp_zero_words(uint32_t *p, uint32_t n)
+{
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+        p[k] = 0;
+}
+
+hipError_t launch_zero_words(uint32_t *p, uint32_t n, hipStream_t stream)
+{
+    hipLaunchKernelGGL(mtgp_zero_words, dim3(1), dim3(64), 0, stream, p, n);
+    return hipGetLastError();
 }
 
 hipError_t opt_in_lds(size_t bytes)

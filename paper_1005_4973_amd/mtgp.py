@@ -93,6 +93,8 @@ _SIGNATURES = {
     "mtgp_batch_create": (ctypes.c_void_p, [ctypes.POINTER(ParamSetC), ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_batch_generate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p]),
     "mtgp_batch_generate_plain": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32, ctypes.c_void_p]),
+    "mtgp_batch_generate_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32,
+                                                  ctypes.c_void_p]),
     "mtgp_batch_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "mtgp_batch_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64]),
     "mtgp_batch_size": (ctypes.c_uint32, [ctypes.c_void_p]),
@@ -326,6 +328,12 @@ class Batch:
         rc = lib().mtgp_batch_generate(self._h, ctypes.cast(arr.ctypes.data, ctypes.POINTER(RequestC)), k,
                                        _stream_ptr(stream))
         _check(rc, "mtgp_batch_generate")
+
+    def generate_static(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
+        """mtgp_batch_generate_static: the same call without jump-ahead and without
+        allocation (work items in the library's fixed per-GPU scratch)."""
+        arr, k = self._reqs(requests)
+        _check(lib().mtgp_batch_generate_static(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate_static")
 
     def generate_plain(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
         arr, k = self._reqs(requests)
