@@ -149,7 +149,10 @@ def measured_traffic(tuning, path=None):
     recorded = dict(kv.split("=") for kv in fields.get("tuning", "").split())
     if recorded.get("split_rounds") != str(tuning["split_rounds"]):
         return None
-    if "mode" in recorded and "mode" in tuning and recorded["mode"] != str(tuning["mode"]):
+    # an explicit shape must be the recorded one (the automatic shape, -1,
+    # resolves from the requests alone, as it did in the counter run)
+    if "mode" in recorded and "mode" in tuning and recorded["mode"] != str(tuning["mode"]) and \
+            int(recorded["mode"]) >= 0 and int(tuning["mode"]) >= 0:
         return None
     return int(fields["traffic_bytes_per_launch"].strip())
 

@@ -251,9 +251,12 @@ void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's la
 /*
  * Autotuner for a request list (unique generators, as for plans). Times `reps`
  * plan launches on `stream` for each candidate configuration -- the automatic
- * launch shape with no split and with split limits halving from the longest
- * request's round count (rounds of the automatic shape) down to 128 rounds
- * (seven halvings, then more only while each one is the fastest so far),
+ * launch shape with no split, with the split limits of one unit's fair share
+ * (all rounds of the request list over the automatic launch's wavefronts or
+ * workgroups) and three quarters of it, and with split limits halving from
+ * the longest request's round count down to 128 rounds (rounds of the
+ * automatic shape; seven halvings, then more only while each one is the
+ * fastest so far),
  * then the chunked form (mode 2) with 64/256/1024 lanes per workgroup and
  * read-ahead 2 (and 256 lanes with read-ahead 1), workgroup forms of
  * 128/256/512/1024 lanes with 1-4 steps per lane and the wavefront form, each

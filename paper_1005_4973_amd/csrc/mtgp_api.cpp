@@ -326,8 +326,10 @@ struct Items {
 // Chunked-form launch for a set of items whose generators it can all run:
 // `threads` lanes per workgroup (one item per wavefront), the least ring
 // that serves every item, and as many workgroups as the items fill, up to
-// kChunkWavesPerCu wavefronts on every CU.
-constexpr uint32_t kChunkWavesPerCu = 16;
+// kChunkWavesPerCu wavefronts on every CU. Two wavefronts a SIMD measured
+// fastest: with more, the output streams written at once multiply and the
+// store throughput falls (16 a CU ran 24 % slower than 8 on uneven batches).
+constexpr uint32_t kChunkWavesPerCu = 8;
 // The automatic shape is the chunked form only with at least this many items
 // per CU: one wavefront per item needs about eight per CU to keep a CU's
 // issue, LDS and stores busy, while with fewer items the workgroup form (four
@@ -1734,20 +1736,35 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
     if (resolve_shape(b, items, ds) != MTGP_OK)
         ds = batch_default_shape(b, items);
     b->have_override = had_override;
-    uint64_t rmax = 0;
+    uint64_t rmax = 0, rsum = 0;
     for (const WorkItem &it : items) {
         const GenRecord &r = b->recs[it.gen];
         const uint32_t W = round_width(r.N, r.M, ds);
         rmax = std::max<uint64_t>(rmax, (it.n + W - 1) / W);
+        rsum += (it.n + W - 1) / W;
     }
     std::vector<Cand> tried;
     Cand c0{true, had_shape, 0, 0.0f};
     trial(c0);
     tried.push_back(c0);
-    // seven halvings; beyond them (requests with millions of rounds) the sweep
-    // goes on while each halving is the fastest configuration so far
+    // the fair share of one unit of the automatic launch (all rounds over its
+    // units), and three quarters of it: with segments about that long the
+    // queue can balance the units with few jumps, where halvings of the
+    // longest request can land far from it
+    const uint64_t units = (uint64_t)std::max(1, ds.grid) * shape_units(ds);
+    const uint64_t share = rsum / std::max<uint64_t>(1, units);
+    for (const uint64_t sr : {share, share * 3 / 4}) {
+        if (!device_ok || sr < 128 || sr >= rmax)
+            continue;
+        Cand c{true, had_shape, (uint32_t)std::min<uint64_t>(sr, UINT32_MAX), 0.0f};
+        trial(c);
+        tried.push_back(c);
+    }
+    // then seven halvings of the longest request's rounds; beyond them
+    // (requests with millions of rounds) the sweep goes on while each halving
+    // is the fastest configuration so far
     for (uint64_t sr = rmax / 2; sr >= 128 && tried.size() < 20 && device_ok; sr /= 2) {
-        if (tried.size() >= 8) {
+        if (tried.size() >= 10) {
             const float last = tried.back().ms;
             bool fastest = last > 0;
             for (const Cand &t : tried)

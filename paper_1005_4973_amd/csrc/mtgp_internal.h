@@ -123,7 +123,7 @@ inline uint32_t chunk_min_gap(uint32_t depth) { return 64u * (depth + 2u); }
 // Ring length of the chunked form for a state of N words: the least power of
 // two L >= max(512, N + 64) (the ring holds the N live words plus a chunk;
 // 512 keeps every block of eight chunks inside one turn of the ring).
-inline uint32_t chunk_ring_words(uint32_t N)
+__host__ __device__ inline uint32_t chunk_ring_words(uint32_t N)
 {
     uint32_t L = 512;
     while (L < N + 64)

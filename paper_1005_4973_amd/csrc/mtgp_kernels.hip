@@ -506,24 +506,30 @@ __device__ __forceinline__ void chunk_stream(uint32_t ringb, uint32_t rtab, uint
     float two = 2.0f;
     if constexpr (KIND == kKindNormal)
         asm("v_mov_b32 %0, 2.0" : "=v"(two));
-    // the start words, each at its slot and L slots on
+    // Ring layout: x_{N+j} sits at slot j mod L and again at slot j mod L + L,
+    // the start words x_k (k < N) at slots L - N + k and 2L - N + k. The slots
+    // a chunk writes are then aligned to the chunk, and the words it reads sit
+    // L - N slots past them, never past slot 2L: inside a block of eight chunks
+    // (512 slots, one part of a turn of the ring) every LDS address is a
+    // register set once per block plus an immediate offset.
     for (uint32_t k = lane; k < N; k += 64) {
         const uint32_t v = hbm_get(from, k);
-        lds_put(ringb + 4u * k, v);
-        lds_put(ringb + 4u * (k + L), v);
+        lds_put(ringb + 4u * (L - N + k), v);
+        lds_put(ringb + 4u * (2u * L - N + k), v);
     }
-    const uint32_t rA = ringb + 4u * lane;        // slot of x_j at ring position 0
-    const uint32_t rC = rA + 4u * (M - 1u);       // slot of x_{j+M-1}
-    const uint32_t wN = 4u * (N + lane);          // 4 (slot of x_{j+N}) before the wrap
-    const float shift = (lane & 1u) ? -1.0f : -0.75f;   // normal kind: angle offsets of cos and sin lanes
+    const uint32_t rA = ringb + 4u * (L - N + lane);   // slot of x_j for the step j = lane
+    const uint32_t rC = rA + 4u * (M - 1u);            // slot of x_{j+M-1}
+    const uint32_t wA = ringb + 4u * lane;             // slot of x_{N+j}
+    const float shift = (lane & 1u) ? -1.0f : -0.75f;  // normal kind: angle offsets of cos and sin lanes
+    // byte offset of chunk q's slots from the ring base
+    auto ring_off = [](uint64_t q) { return 4u * ((64u * (uint32_t)q) & (L - 1u)); };
 
-    auto reads = [&](uint64_t q) {
-        const uint32_t s = 4u * ((64u * (uint32_t)q) & (L - 1u));
+    auto reads = [&](uint32_t pa, uint32_t pc) {
         ChunkIn c;
-        c.a = lds_get(rA + s);
-        c.b = lds_get(rA + s + 4u);
-        c.c = lds_get(rC + s);
-        c.d = lds_get(rC + s + 4u);
+        c.a = lds_get(pa);
+        c.b = lds_get(pa + 4u);
+        c.c = lds_get(pc);
+        c.d = lds_get(pc + 4u);
         return c;
     };
     auto compute = [&](const ChunkIn &c) {
@@ -532,18 +538,22 @@ __device__ __forceinline__ void chunk_stream(uint32_t ringb, uint32_t rtab, uint
         m.u = __builtin_amdgcn_bitop3_b32(a << sh1, c.d >> sh2, a, (uint8_t)0x96);
         m.r = lds_get(((m.u << 2) & 0x3cu) | rtab);
         if constexpr (KIND != kKindRaw) {
-            uint32_t t = c.c ^ (c.c >> 16);
-            t ^= t >> 8;
+            // only the low four bits of the index count, so each fold is one
+            // XOR with a halfword or byte operand select (the compiler finds
+            // the first and not the second)
+            const uint32_t h = c.c ^ (c.c >> 16);
+            uint32_t t;
+            asm("v_xor_b32_sdwa %0, %1, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+                : "=v"(t)
+                : "v"(h));
             m.t = lds_get(((t << 2) & 0x3cu) | otab);
         } else {
             m.t = 0;
         }
         return m;
     };
-    auto finish = [&](uint64_t q, const ChunkMid &m, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    auto finish = [&](uint32_t w, const ChunkMid &m, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
         const uint32_t x = m.u ^ m.r;
-        const uint32_t s = 4u * ((64u * (uint32_t)q) & (L - 1u));
-        const uint32_t w = ((wN + s) & (4u * L - 1u)) | ringb;
         lds_put(w, x);
         lds_put(w + 4u * L, x);
         uint32_t o = output_word<KIND>(x, m.t);
@@ -566,24 +576,26 @@ __device__ __forceinline__ void chunk_stream(uint32_t ringb, uint32_t rtab, uint
     ChunkMid mid[CA];
 #pragma unroll
     for (uint32_t k = 0; k < RA; k++)
-        in[k] = reads(k);
+        in[k] = reads(rA + 256u * k, rC + 256u * k);
 #pragma unroll
     for (uint32_t k = 0; k < CA; k++) {
         mid[k] = compute(in[0]);
 #pragma unroll
         for (uint32_t r = 0; r + 1 < RA; r++)
             in[r] = in[r + 1];
-        in[RA - 1] = reads(RA + k);
+        in[RA - 1] = reads(rA + 256u * (RA + k), rC + 256u * (RA + k));
     }
-    auto step = [&](uint64_t q, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    // one iteration: the reads of a later chunk at (pa, pc), the computation
+    // of the next chunk up to its lookups, and this chunk's words to slot w
+    auto step = [&](uint32_t pa, uint32_t pc, uint32_t w, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
         // the stages stay in this order: left to itself, the scheduler
         // moves each chunk's computation next to its reads, and the
         // pipeline becomes a wait for every read
-        const ChunkIn fresh = reads(q + CA + RA);
+        const ChunkIn fresh = reads(pa, pc);
         __builtin_amdgcn_sched_barrier(0);
         const ChunkMid m = compute(in[0]);
         __builtin_amdgcn_sched_barrier(0);
-        finish(q, mid[0], rs, off);
+        finish(w, mid[0], rs, off);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (uint32_t r = 0; r + 1 < RA; r++)
@@ -594,21 +606,56 @@ __device__ __forceinline__ void chunk_stream(uint32_t ringb, uint32_t rtab, uint
             mid[r] = mid[r + 1];
         mid[CA - 1] = m;
     };
+    constexpr uint32_t F = CA + RA;   // the fresh reads are F chunks ahead
+    static_assert(F < 8, "read-ahead within one block");
     uint64_t q = 0;
     // blocks of eight chunks: one output window (the range check drops the
-    // stores of steps >= n), stores at immediate offsets
+    // stores of steps >= n), stores at immediate offsets; the block's slots
+    // start at a0 and the next block's at a1 (the same for a 512-slot ring)
+    uint32_t a0 = 0;
     for (; q + 8 <= Q; q += 8) {
+        const uint32_t a1 = L == 512 ? 0u : (a0 + 2048u) & (4u * L - 1u);
+        const uint32_t pa0 = rA + a0, pc0 = rC + a0, pa1 = rA + a1, pc1 = rC + a1, w0 = wA + a0;
         const __amdgpu_buffer_rsrc_t rs = out_window(out + 64 * q, (uint32_t)std::min<uint64_t>(n - 64 * q, 512));
 #pragma unroll
-        for (uint32_t j = 0; j < 8; j++)
-            step(q + j, rs, 256u * j);
+        for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t f = j + F;
+            if (f < 8)
+                step(pa0 + 256u * f, pc0 + 256u * f, w0 + 256u * j, rs, 256u * j);
+            else
+                step(pa1 + 256u * (f - 8u), pc1 + 256u * (f - 8u), w0 + 256u * j, rs, 256u * j);
+        }
+        a0 = a1;
     }
-    for (; q < Q; q++)
-        step(q, out_window(out + 64 * q, (uint32_t)std::min<uint64_t>(n - 64 * q, 64)), 0);
+    for (; q < Q; q++) {
+        const uint32_t af = ring_off(q + F);
+        step(rA + af, rC + af, wA + ring_off(q), out_window(out + 64 * q, (uint32_t)std::min<uint64_t>(n - 64 * q, 64)),
+             0);
+    }
     // x_n .. x_{n+N-1} back to HBM (section 8: the next call continues)
     if (state != nullptr)
         for (uint32_t k = lane; k < N; k += 64)
-            hbm_put(state, k, lds_get(ringb + 4u * ((uint32_t)(n + k) & (L - 1u))));
+            hbm_put(state, k, lds_get(ringb + 4u * (((uint32_t)n + k + L - N) & (L - 1u))));
+}
+
+// One item in a ring of L words, dispatched on its output kind.
+template <uint32_t L, uint32_t RA, uint32_t CA>
+__device__ __forceinline__ void chunk_kind(uint32_t kind, uint32_t ringb, uint32_t rtab, uint32_t otab, uint32_t N,
+                                           uint32_t M, const GenRecord &g, uint64_t n, gu32 *out, uint32_t *state,
+                                           const uint32_t *from, uint32_t lane)
+{
+#define MTGP_CHUNK(K) chunk_stream<K, L, RA, CA>(ringb, rtab, otab, N, M, g.sh1, g.sh2, g.mask, n, out, state, from, lane)
+    if (kind == kKindU32)
+        MTGP_CHUNK(kKindU32);
+    else if (kind == kKindF12)
+        MTGP_CHUNK(kKindF12);
+    else if (kind == kKindF01)
+        MTGP_CHUNK(kKindF01);
+    else if (kind == kKindNormal)
+        MTGP_CHUNK(kKindNormal);
+    else
+        MTGP_CHUNK(kKindRaw);
+#undef MTGP_CHUNK
 }
 
 // The chunked form's kernel: each wavefront pops work items like the wave
@@ -669,19 +716,19 @@ __global__ __launch_bounds__(1024) void mtgp_chunk_kernel(const GenRecord *__res
                 hbm_put(out, k, hbm_get(from, k));
             out += N;
         }
-#define MTGP_CHUNK(K) \
-    chunk_stream<K, L, RA, CA>(ringb, rtab, otab, N, M, g.sh1, g.sh2, g.mask, it.n, out, state, from, lane)
-        if (kind == kKindU32)
-            MTGP_CHUNK(kKindU32);
-        else if (kind == kKindF12)
-            MTGP_CHUNK(kKindF12);
-        else if (kind == kKindF01)
-            MTGP_CHUNK(kKindF01);
-        else if (kind == kKindNormal)
-            MTGP_CHUNK(kKindNormal);
+        // each item runs in the ring its own state needs (the wavefront's LDS
+        // region is sized for the launch's largest): with a 512-word ring a
+        // block of eight chunks is one turn of the ring, and the compiler
+        // keeps every LDS address of the block in registers
+        const uint32_t LI = chunk_ring_words(N);
+        if (LI <= 512 || L == 512)
+            chunk_kind<(L < 512 ? L : 512), RA, CA>(kind, ringb, rtab, otab, N, M, g, it.n, out, state, from, lane);
+        else if (LI <= 1024 || L == 1024)
+            chunk_kind<(L < 1024 ? L : 1024), RA, CA>(kind, ringb, rtab, otab, N, M, g, it.n, out, state, from, lane);
+        else if (LI <= 2048 || L == 2048)
+            chunk_kind<(L < 2048 ? L : 2048), RA, CA>(kind, ringb, rtab, otab, N, M, g, it.n, out, state, from, lane);
         else
-            MTGP_CHUNK(kKindRaw);
-#undef MTGP_CHUNK
+            chunk_kind<L, RA, CA>(kind, ringb, rtab, otab, N, M, g, it.n, out, state, from, lane);
     }
     // queue reset by the last unit to finish (as in mtgp_kernel)
     if (items != nullptr && counters != nullptr && lane == 0) {
