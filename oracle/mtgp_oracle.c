@@ -31,7 +31,14 @@
  *
  * Evaluation here is the definition itself: an array x[0 .. N+n) is filled in
  * index order, x[N+i] from x[M+i], x[1+i] and x[i] (section 3.1), and each
- * output is tempered with x[M-1+i].
+ * output is tempered with x[M-1+i]. The two products with 4 x w matrices
+ * (the recursion's (u's four LSBs) R and the tempering's (t's four LSBs) T)
+ * are formed as the definitions state them, a row vector times a matrix:
+ * the XOR of the rows of R (or T) that the four bits select. The parameter
+ * set carries R and T as the 16 products (0000)R .. (1111)R (and likewise
+ * for T), as the paper stores them; the rows are read off the products of
+ * the unit vectors, and a table that is not the product table of its rows is
+ * rejected.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -58,18 +65,52 @@ void orc_seed(uint32_t seed, uint32_t nwords, uint32_t *x)
         x[i] = 1812433253u * (x[i - 1] ^ (x[i - 1] >> 30)) + i;
 }
 
+/* A 4 x 32 matrix over F2 as its rows row[0] (top) .. row[3] (bottom). */
+typedef struct {
+    uint32_t row[4];
+} orc_mat4;
+
+/* The row vector (b_0 b_1 b_2 b_3) of the four LSBs of v, written most
+ * significant first (b_0 = bit 3 of v, b_3 = bit 0), times the matrix:
+ * the XOR of the rows j with b_j = 1 (sections 3.6 and 3.7). */
+static uint32_t orc_vec4_times(uint32_t v, const orc_mat4 *a)
+{
+    uint32_t acc = 0;
+    for (int j = 0; j < 4; j++)
+        if ((v >> (3 - j)) & 1u)
+            acc ^= a->row[j];
+    return acc;
+}
+
+/* The matrix whose product table is tbl[0..15] (tbl[v] = (v as a 4-bit row
+ * vector) times the matrix): row j is the product of the unit vector with its
+ * one at position j, i.e. tbl[1 << (3 - j)]. Returns -1 if tbl is not the
+ * product table of those rows (it then describes no matrix). */
+static int orc_matrix_of(const uint32_t tbl[16], orc_mat4 *a)
+{
+    for (int j = 0; j < 4; j++)
+        a->row[j] = tbl[1u << (3 - j)];
+    for (uint32_t v = 0; v < 16; v++)
+        if (orc_vec4_times(v, a) != tbl[v])
+            return -1;
+    return 0;
+}
+
 /* One output word of kind `kind` from x_{N+i} (new word) and x_{M-1+i}
- * (the tempering word), section 3.7 and section 6. */
-static uint32_t orc_output(const orc_params *p, uint32_t x_new, uint32_t x_tmp, int kind)
+ * (the tempering word), section 3.7 (Definition of the tempering parameter)
+ * and section 6. */
+static uint32_t orc_output(const orc_mat4 *T, uint32_t x_new, uint32_t x_tmp, int kind)
 {
     uint32_t t = x_tmp ^ (x_tmp >> 16);
     t = t ^ (t >> 8);
+    const uint32_t h = orc_vec4_times(t, T);   /* h(x_{M-1+i}) = (t's four LSBs) T */
     if (kind == ORC_U32)
-        return x_new ^ p->temper_tbl[t & 0xf];
+        return x_new ^ h;
 
-    /* Section 6: sngltbl[k] has the nine MSBs 001111111 and then the 23 MSBs
-     * of tmptbl[k]; the output is (x >> 9) ^ sngltbl[t & 0xf]. */
-    uint32_t sngl = 0x3f800000u | (p->temper_tbl[t & 0xf] >> 9);
+    /* Section 6: the single-precision table entry has the nine MSBs
+     * 001111111 and then the 23 MSBs of the tempering value; the output is
+     * (x >> 9) ^ that entry. */
+    uint32_t sngl = 0x3f800000u | (h >> 9);
     uint32_t bits = (x_new >> 9) ^ sngl;
     if (kind == ORC_F12)
         return bits;
@@ -96,6 +137,9 @@ int orc_generate(const orc_params *p, uint32_t *state, uint64_t n, int kind, uin
     const uint64_t M = p->pos;
     if (M < 2 || M > N - 1)
         return -1;
+    orc_mat4 R, T;
+    if (orc_matrix_of(p->param_tbl, &R) != 0 || orc_matrix_of(p->temper_tbl, &T) != 0)
+        return -1;
     const uint32_t r = (uint32_t)(32u * N - p->mexp);
     const uint32_t mask = 0xffffffffu << r;   /* BITMASK(w,r): w-r MSBs set */
 
@@ -105,13 +149,15 @@ int orc_generate(const orc_params *p, uint32_t *state, uint64_t n, int kind, uin
     memcpy(x, state, (size_t)N * sizeof(uint32_t));
 
     for (uint64_t i = 0; i < n; i++) {
-        /* recursion, section 3.6 (C form), computed in this order */
+        /* recursion, section 3.6 (Definition of the recursion parameters),
+         * its four steps in the stated order: the w - r MSBs of x_i with r
+         * zero bits, the sh1 and sh2 shifts, then u plus (u's four LSBs) R */
         uint32_t t = x[1 + i] ^ (x[i] & mask);
         t = t ^ (t << p->sh1);
         uint32_t u = t ^ (x[M + i] >> p->sh2);
-        x[N + i] = u ^ p->param_tbl[u & 0xf];
+        x[N + i] = u ^ orc_vec4_times(u, &R);
         /* tempering with x_{M-1+i}, section 3.7 */
-        out[i] = orc_output(p, x[N + i], x[M - 1 + i], kind);
+        out[i] = orc_output(&T, x[N + i], x[M - 1 + i], kind);
     }
 
     memcpy(state, x + n, (size_t)N * sizeof(uint32_t));

@@ -302,22 +302,40 @@ class Batch:
 
     @staticmethod
     def _reqs(requests: Iterable):
+        """Requests as the C array, its length and the output tensors it points
+        into. A tensor output is checked like Generator.generate's (a contiguous
+        4-byte CUDA tensor on the current device with at least n elements); an
+        integer output is a device address that the caller vouches for: at
+        least 4 n bytes, 4-byte aligned, alive until the work has run."""
         reqs = list(requests)
         arr = (RequestC * max(1, len(reqs)))()
+        tensors = []
         for i, (gen, kind, n, out) in enumerate(reqs):
-            ptr = out.data_ptr() if isinstance(out, torch.Tensor) else int(out)
+            if isinstance(out, torch.Tensor):
+                _out_tensor(n, kind, out, "cuda")
+                if out.device.index != torch.cuda.current_device():
+                    raise ValueError("out must be on the current CUDA device")
+                ptr = out.data_ptr()
+                tensors.append(out)
+            else:
+                ptr = int(out)
             arr[i].gen, arr[i].kind, arr[i].n, arr[i].out = gen, kind, n, ptr
-        return arr, len(reqs)
+        return arr, len(reqs), tensors
 
     def generate(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
         """requests: iterable of (gen, kind, n, out tensor or device address). With a split
-        limit set, a call holding a longer request runs as jump-ahead segments."""
-        arr, k = self._reqs(requests)
+        limit set, a call holding a longer request runs as jump-ahead segments. The call is
+        stream-ordered: the output tensors must outlive the work (hold them, or use them on
+        the same stream, until it has run)."""
+        arr, k, _ = self._reqs(requests)
         _check(lib().mtgp_batch_generate(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate")
 
     def generate_arrays(self, gens, kinds, ns, ptrs, stream: Optional[torch.cuda.Stream] = None):
         """Same as generate, with the requests as equal-length integer arrays
-        (generator, kind, n, output device address): no per-request Python work."""
+        (generator, kind, n, output device address): no per-request Python work.
+        The addresses are the caller's responsibility, as integer outputs of
+        generate are (at least 4 n bytes each, 4-byte aligned, alive until the
+        work has run); the library checks alignment and nothing else about them."""
         import numpy as np
         k = len(gens)
         arr = np.zeros(k, dtype=REQUEST_DTYPE)
@@ -332,11 +350,11 @@ class Batch:
     def generate_static(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
         """mtgp_batch_generate_static: the same call without jump-ahead and without
         allocation (work items in the library's fixed per-GPU scratch)."""
-        arr, k = self._reqs(requests)
+        arr, k, _ = self._reqs(requests)
         _check(lib().mtgp_batch_generate_static(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate_static")
 
     def generate_plain(self, requests: Iterable, stream: Optional[torch.cuda.Stream] = None):
-        arr, k = self._reqs(requests)
+        arr, k, _ = self._reqs(requests)
         _check(lib().mtgp_batch_generate_plain(self._h, arr, k, _stream_ptr(stream)), "mtgp_batch_generate_plain")
 
     def set_split(self, max_rounds: int):
@@ -347,7 +365,7 @@ class Batch:
     def autotune(self, requests: Iterable, reps: int = 5, stream: Optional[torch.cuda.Stream] = None) -> dict:
         """Time candidate launch shapes and split limits on these requests and keep
         the fastest (mtgp_batch_autotune); streams are left where they were."""
-        arr, k = Batch._reqs(requests)
+        arr, k, _ = Batch._reqs(requests)
         t = TuningC()
         _check(lib().mtgp_batch_autotune(self._h, arr, k, _stream_ptr(stream), reps, ctypes.byref(t)),
                "mtgp_batch_autotune")
@@ -389,10 +407,12 @@ class Batch:
 
 class Plan:
     """A fixed request list whose persistent launch is captured in a HIP graph
-    (mtgp_batch_plan_create); each launch() continues every listed stream."""
+    (mtgp_batch_plan_create); each launch() continues every listed stream.
+    Every replay writes the listed outputs: the plan holds its output tensors
+    for its lifetime (integer addresses stay the caller's to keep valid)."""
 
     def __init__(self, batch: Batch, requests: Iterable):
-        arr, k = Batch._reqs(requests)
+        arr, k, self._outs = Batch._reqs(requests)
         self.batch = batch
         self._h = lib().mtgp_batch_plan_create(batch._h, arr, k)
         if not self._h:

@@ -84,3 +84,18 @@ def test_create_rejects_bad_parameters_before_touching_the_device():
         with pytest.raises(mtgp.MTGPError) as e:
             mtgp.Generator(b, 1)
         assert e.value.code == mtgp.MTGP_EINVAL
+
+
+def test_request_tensors_are_checked_before_the_call():
+    """Batch requests with tensor outputs get the same checks as a single
+    generator's output (CUDA, contiguous, 4-byte elements, at least n of
+    them): a bad tensor is refused in Python, before any pointer reaches the
+    library; integer addresses pass through unchecked (the caller's)."""
+    import torch
+    from paper_1005_4973_amd import mtgp
+    host = torch.empty(100, dtype=torch.int32)
+    for bad in (host, host.to(torch.int16), host[::2]):
+        with pytest.raises(ValueError):
+            mtgp.Batch._reqs([(0, mtgp.KIND_UINT32, 10, bad)])
+    arr, k, tensors = mtgp.Batch._reqs([(0, mtgp.KIND_UINT32, 10, 0x1000), (1, mtgp.KIND_FLOAT32_0TO1, 0, 0x2000)])
+    assert k == 2 and tensors == [] and arr[0].out == 0x1000 and arr[1].n == 0

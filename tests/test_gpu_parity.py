@@ -231,16 +231,28 @@ def test_launch_shapes_parity(M):
     b = M.Batch(params, seeds)
     states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
     rng = I.SplitMix64(99)
-    for sh in SHAPES:
+    for i, sh in enumerate(SHAPES):
         say(f"shape {sh}")
         b.set_launch(*sh)
-        reqs = [(g, g % 3, rng.uniform_int(1, 9000)) for g in range(len(params))]
+        reqs = []
+        for g in range(len(params)):
+            # every kind under every shape; normals in even counts, where
+            # N - M >= 2 leaves room for a pair in a round
+            k = (g + i) % 4
+            if k == 3 and O.nwords(params[g].mexp) - params[g].pos < 2:
+                k = 0
+            n = rng.uniform_int(1, 9000)
+            reqs.append((g, k, n + (n & 1) if k == 3 else n))
         bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
         b.generate([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
         torch.cuda.synchronize()
         for (g, k, n), buf in zip(reqs, bufs):
-            ref = O.generate(params[g], states[g], n, k)
-            np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"shape={sh} gen={g}")
+            if k == 3:
+                err = np.abs(host_f32(buf) - O.normals(params[g], states[g], n)).max()
+                assert err <= NORMAL_ATOL, f"shape={sh} gen={g} normal err={err}"
+            else:
+                ref = O.generate(params[g], states[g], n, k)
+                np.testing.assert_array_equal(host_bits(buf), ref, err_msg=f"shape={sh} gen={g}")
     b.set_launch(-1)
     for g in range(len(params)):
         np.testing.assert_array_equal(b.get_state(g)[0], states[g])
@@ -507,13 +519,21 @@ def test_normals_single_generator_and_continuation(M):
     g.close()
 
 
-def test_normals_batch_and_split_plan(M):
+@pytest.mark.parametrize("shape", [None, (1 | RB, 64, 16, 0, 0), (RB, 256, 4, 0, 0)])
+def test_normals_batch_and_split_plan(M, shape):
+    """Normals beside the other kinds in an eager batch and as a split plan,
+    under the automatic shape, the wavefront form with the recursion basis
+    (pairs split across DPP lanes, rounds of W & ~1 steps) and the workgroup
+    form with the recursion basis."""
     import torch
+    say(f"normals under shape {shape}")
     params = I.draw_param_sets([11213] * 3 + [23209, 44497], 93)
     seeds = I.state_seeds(len(params))
     states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(len(params))}
     rng = I.SplitMix64(94)
     b = M.Batch(params, seeds)
+    if shape is not None:
+        b.set_launch(*shape)
     # eager batch: normals beside the other kinds, even ragged lengths
     reqs = [(g, [3, 0, 3, 1, 3][g], 2 * rng.uniform_int(1, 30000)) for g in range(len(params))]
     bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]

@@ -31,8 +31,9 @@ def table_of(rows):
 
 
 # ---------------------------------------------------------------------------
-# Worked examples traced by hand from section 3.6 (recursion, C form) and
-# section 3.7 (tempering). N = 3 (p = 89, r = 7, BITMASK = 0xffffff80), M = 2.
+# Worked examples traced by hand from section 3.6 (recursion) and section 3.7
+# (tempering), the products with R and T written as their product tables
+# (rectbl, tmptbl). N = 3 (p = 89, r = 7, BITMASK = 0xffffff80), M = 2.
 # ---------------------------------------------------------------------------
 
 def test_hand_trace_small_words():
@@ -72,11 +73,13 @@ def test_hand_trace_mask_and_tempering_shifts():
 
 
 # ---------------------------------------------------------------------------
-# Two readings of the paper agree: C form (oracle) vs matrix form (pyref).
+# Two readings of the paper agree: the oracle (the definitions' steps, the
+# 4 x w products by row selection) vs pyref (the transition and output as
+# bit matrices).
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mexp", [65, 89, 107, 127, 521, 607, 608])
-def test_c_form_equals_matrix_form(mexp):
+def test_definition_steps_equal_matrix_form(mexp):
     # 65 and 608 are the extremes of the mask: r = 31 (one bit of x_i kept)
     # and r = 0 (the whole word)
     for s in range(3):
@@ -378,9 +381,16 @@ def test_oracle_rejects_out_of_definition_parameters():
     ps = I.single_stream()[0][0]
     N = O.nwords(ps.mexp)
     st = O.seed_state(1, ps.mexp)
+    # tables must be the products (v)R and (v)T of 4 x w matrices (sections
+    # 3.6 and 3.7): one flipped bit in an entry that is not a unit vector's
+    # product leaves no matrix with that table
+    flip = lambda t, v: t[:v] + (t[v] ^ 0x40,) + t[v + 1:]
     for bad in (I.ParamSet(ps.mexp, 1, 1, 1, ps.param_tbl, ps.temper_tbl),
                 I.ParamSet(ps.mexp, N, 1, 1, ps.param_tbl, ps.temper_tbl),
-                I.ParamSet(ps.mexp, 5, 32, 1, ps.param_tbl, ps.temper_tbl)):
+                I.ParamSet(ps.mexp, 5, 32, 1, ps.param_tbl, ps.temper_tbl),
+                I.ParamSet(ps.mexp, ps.pos, ps.sh1, ps.sh2, flip(ps.param_tbl, 7), ps.temper_tbl),
+                I.ParamSet(ps.mexp, ps.pos, ps.sh1, ps.sh2, ps.param_tbl, flip(ps.temper_tbl, 12)),
+                I.ParamSet(ps.mexp, ps.pos, ps.sh1, ps.sh2, flip(ps.param_tbl, 0), ps.temper_tbl)):
         with pytest.raises(ValueError):
             O.generate(bad, st.copy(), 4)
 
