@@ -128,10 +128,20 @@ TRAFFIC_PROFILE_128 = os.path.join(ROOT, "profiles", "mtgp_chunk_kernel_independ
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1005_4973_amd", "csrc", f) for f in ("mtgp_kernels.hip", "mtgp_internal.h")]
 
 
-def measured_traffic(tuning, path=None):
+def launch_of(info):
+    """The resolved generation launch of a plan (mtgp_plan_describe) as the
+    fields a counter summary records."""
+    return {k: info[k] for k in ("mode", "threads", "spl", "lds_words", "grid")}
+
+
+def launch_str(launch):
+    return " ".join(f"{k}={launch[k]}" for k in ("mode", "threads", "spl", "lds_words", "grid"))
+
+
+def measured_traffic(launch, split_rounds, path=None):
     """HBM bytes per launch of a generation kernel from a committed counter
-    summary, or None when the kernel sources or the tuned configuration
-    differ from those the counters were taken with."""
+    summary, or None when the kernel sources, the split limit (which sets the
+    segments) or the resolved launch differ from those of the counter run."""
     import hashlib
     try:
         text = open(path or TRAFFIC_PROFILE).read()
@@ -141,30 +151,44 @@ def measured_traffic(tuning, path=None):
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
     fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:", "tuning:")))
+                  if line.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:", "split_rounds:",
+                                      "launch:")))
     if fields.get("kernel_source_sha256_16", "").split()[0:1] != [h.hexdigest()[:16]]:
         return None
-    # the split limit sets the segments whose start states the kernel reads,
-    # and the launch shape the round unit the split limit counts in
-    recorded = dict(kv.split("=") for kv in fields.get("tuning", "").split())
-    if recorded.get("split_rounds") != str(tuning["split_rounds"]):
+    if fields.get("split_rounds", "").strip() != str(split_rounds):
         return None
-    # an explicit shape must be the recorded one (the automatic shape, -1,
-    # resolves from the requests alone, as it did in the counter run)
-    if "mode" in recorded and "mode" in tuning and recorded["mode"] != str(tuning["mode"]) and \
-            int(recorded["mode"]) >= 0 and int(tuning["mode"]) >= 0:
+    if fields.get("launch", "").strip() != launch_str(launch):
         return None
     return int(fields["traffic_bytes_per_launch"].strip())
 
 
-def kernel_name(tuning):
-    """The generation kernel a tuned plan launches (for the roofline line)."""
-    mode = tuning["mode"]
-    if mode >= 0 and (mode & 3) == 2:
-        return "mtgp_chunk_kernel (chunked wavefront form, read-ahead {})".format(tuning["spl"])
-    if mode < 0:
-        return "generation kernel of the automatic shape"
+def kernel_name(launch):
+    """The generation kernel a plan launches (for the roofline line)."""
+    mode = launch["mode"]
+    if (mode & 3) == 2:
+        return "mtgp_chunk_kernel<{}, {}, 1>".format(launch["lds_words"], launch["spl"])
     return "mtgp_kernel<{}, {}>".format("true" if mode & 1 else "false", "true" if mode & 4 else "false")
+
+
+def store_ceilings(torch, outs, ns, launch, fill=None):
+    """Write ceilings of a plan's output layout: the store-only probe over the
+    plan's own work items in queue order, on as many wavefronts as the launch
+    runs items at once, with 4-byte plain stores (the generation kernels'
+    pattern), 4-byte nontemporal and 16-byte plain stores; and a torch fill
+    of the output buffer when given. GB/s of output bytes."""
+    from paper_1005_4973_amd import probe
+    units = launch["threads"] // 64 if launch["mode"] & 3 else 1
+    waves = launch["grid"] * units
+    nbytes = 4 * int(sum(int(v) for v in ns))
+    res = {"waves": waves}
+    for key, width, nt in (("probe_4B_plain", 1, False), ("probe_4B_nontemporal", 1, True),
+                           ("probe_16B_plain", 4, False)):
+        ms = probe.store_ms(outs, ns, waves, width, nt, reps=3)
+        res[key] = round(nbytes / ms / 1e6, 1)
+    if fill is not None:
+        fill_ms = timed_ms(torch, lambda: fill.fill_(7), reps=5, warmup=1)
+        res["torch_fill"] = round(4 * fill.numel() / fill_ms / 1e6, 1)
+    return res
 
 
 def phase_times(torch, plan, mtgp, stream, reps, warmup):
@@ -193,20 +217,21 @@ def median(v):
     return v[k] if len(v) % 2 else 0.5 * (v[k - 1] + v[k])
 
 
-def roofline_block(alg_bytes, gen_ms, step_ms, tuning, traffic, store_gbs=None):
+def roofline_block(alg_bytes, gen_ms, step_ms, launch, traffic, ceilings=None):
     """`roofline` object for a generation kernel: algorithmic bytes per launch
     over its average launch time, against the 8 TB/s HBM peak; the whole
-    replay (prepare and generate) beside it."""
+    replay (prepare and generate) beside it, and the store-only ceilings of
+    the same output layout when measured."""
     achieved = alg_bytes / (gen_ms / 1e3) / 1e9
     blk = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_name(tuning),
-           "avg_launch_ms": round(gen_ms, 4), "alg_bytes_per_launch": alg_bytes,
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_name(launch),
+           "launch": launch, "avg_launch_ms": round(gen_ms, 4), "alg_bytes_per_launch": alg_bytes,
            "end_to_end": {"ms_per_replay": round(step_ms, 4),
                           "GBs": round(alg_bytes / (step_ms / 1e3) / 1e9, 1),
                           "frac": round(alg_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
-    if store_gbs:
-        blk["store_ceiling_GBs"] = round(store_gbs, 1)
-        blk["frac_of_store_ceiling"] = round(achieved / store_gbs, 4)
+    if ceilings:
+        blk["store_ceilings_GBs"] = ceilings
+        blk["frac_of_store_ceiling"] = round(achieved / ceilings["probe_4B_plain"], 4)
     return blk
 
 
@@ -255,14 +280,15 @@ def headline(args, torch, I, mtgp, ctx):
     tune_s = time.perf_counter() - t0
     log(f"autotune: {tuning} in {tune_s:.1f} s")
     plan = batch.plan(rq)
+    launch = launch_of(plan.describe())
+    outs, ns = plan.items()
     times, wall = phase_times(torch, plan, mtgp, stream, args.steps, args.warmup)
     plan.close()
     prep = sum(t[0] for t in times) / len(times)
     gen = sum(t[1] for t in times) / len(times)
-    # store-only ceiling: a torch fill of the same output buffer
-    fill_ms = timed_ms(torch, lambda: out.fill_(7), reps=5, warmup=1)
+    ceilings = store_ceilings(torch, outs, ns, launch, fill=out)
     alg = workload_bytes(params, reqs)
-    ctx.update(params=params, reqs=reqs, batch=batch, out=out, tuning=tuning)
+    ctx.update(params=params, reqs=reqs, batch=batch, out=out, tuning=tuning, launch=launch)
     return {
         "value": round(tot * args.steps / wall / 1e9, 3),
         "ms_per_step": round(wall / args.steps * 1e3, 4),
@@ -273,8 +299,8 @@ def headline(args, torch, I, mtgp, ctx):
                                "generation launch)",
                    "generators": G, "numbers_per_step": tot, "bytes_per_step": 4 * tot,
                    "autotuned": tuning, "autotune_s": round(tune_s, 1)},
-        "roofline": {**roofline_block(alg, gen, wall / args.steps * 1e3, tuning,
-                                      measured_traffic(tuning, TRAFFIC_PROFILE), 4 * tot / fill_ms / 1e6),
+        "roofline": {**roofline_block(alg, gen, wall / args.steps * 1e3, launch,
+                                      measured_traffic(launch, tuning["split_rounds"], TRAFFIC_PROFILE), ceilings),
                      "avg_prepare_ms": round(prep, 4)},
     }
 
@@ -299,15 +325,19 @@ def independent_128(torch, I, mtgp, ctx):
     steps = []
     for k, name in zip(kinds, ("uint32", "float32_1to2", "float32_0to1")):
         plan = batch.plan(reqs[k])
+        launch = launch_of(plan.describe())
+        outs, ns = plan.items()
         times, wall = phase_times(torch, plan, mtgp, stream, 10, 3)
         plan.close()
         step = median([a + b for a, b in times])
         gen = median([b for a, b in times])
         steps.append(step)
+        ceilings = store_ceilings(torch, outs, ns, launch) if k == I.KIND_U32 else None
         res["kinds"][name] = {"ms": round(step, 4), "G_numbers_s": round(G * n / step / 1e6, 2),
-                              "roofline": {**roofline_block(alg, gen, step, tuning,
-                                                            measured_traffic(tuning, TRAFFIC_PROFILE_128)
-                                                            if k == I.KIND_U32 else None),
+                              "roofline": {**roofline_block(alg, gen, step, launch,
+                                                            measured_traffic(launch, tuning["split_rounds"],
+                                                                             TRAFFIC_PROFILE_128)
+                                                            if k == I.KIND_U32 else None, ceilings),
                                            "avg_prepare_ms": round(median([a for a, b in times]), 4)}}
     res["G_numbers_s_three_kinds"] = round(3 * G * n / sum(steps) / 1e6, 2)
     batch.close()
@@ -320,7 +350,8 @@ def batched_plain(torch, I, mtgp, ctx):
     """The headline workload as one launch per request on one stream (one
     workgroup per generator, as the paper runs one block per generator), and
     the critical path of the tuned plan: its longest segment timed alone."""
-    params, reqs, batch, out, tuning = (ctx[k] for k in ("params", "reqs", "batch", "out", "tuning"))
+    params, reqs, batch, out, tuning, launch = (ctx[k] for k in ("params", "reqs", "batch", "out", "tuning",
+                                                                  "launch"))
     tot = sum(r.n for r in reqs)
     base = out.data_ptr()
     rq = [(r.gen, r.kind, r.n, base + 4 * r.offset) for r in reqs]
@@ -334,7 +365,7 @@ def batched_plain(torch, I, mtgp, ctx):
     r_max, crit = 0, None
     for r in reqs:
         ps = params[r.gen]
-        W = round_width(state_words(ps.mexp), ps.pos, tuning)
+        W = round_width(state_words(ps.mexp), ps.pos, launch)
         rounds = -(-r.n // W)
         S = -(-rounds // tuning["split_rounds"]) if tuning["split_rounds"] else 1
         J = -(-r.n // S)
@@ -360,17 +391,17 @@ def state_words(mexp):
     return (mexp + 31) // 32
 
 
-def round_width(N, M, tuning):
-    """Steps a round of this generator computes under a tuned launch shape:
-    W = min(N - M, lanes * s), s the largest steps per lane allowed by the
-    shape with lanes * s <= N - M (the library's own rule)."""
-    mode = tuning["mode"]
-    if mode >= 0 and (mode & 3) == 2:
-        return 64   # chunked form: a round is one chunk of 64 steps
+def round_width(N, M, launch):
+    """Steps a round of this generator computes under a resolved launch shape
+    (mtgp_plan_describe): W = min(N - M, lanes * s), s the largest steps per
+    lane allowed by the shape with lanes * s <= N - M (the library's own
+    rule); a chunk of 64 steps in the chunked form."""
+    mode = launch["mode"]
     if mode < 0:
-        wave, threads, cap = False, 256, 4
-    else:
-        wave, threads, cap = bool(mode & 1), tuning["threads"], tuning["spl"]
+        raise ValueError("round_width needs a resolved launch shape")
+    if (mode & 3) == 2:
+        return 64
+    wave, threads, cap = bool(mode & 1), launch["threads"], launch["spl"]
     lanes = 64 if wave else threads
     cands = (16, 12, 8, 6, 4, 2, 1) if wave else (4, 2, 1)
     s = next((c for c in cands if c <= cap and lanes * c <= N - M), 1)
@@ -390,8 +421,11 @@ def large_states(torch, I, mtgp, ctx):
         tuning = batch.autotune(rq, reps=2, stream=stream)
         tune_s = time.perf_counter() - t0
         plan = batch.plan(rq)
+        launch = launch_of(plan.describe())
+        outs, ns = plan.items()
         times, wall = phase_times(torch, plan, mtgp, stream, 10, 3)
         plan.close()
+        ceilings = store_ceilings(torch, outs, ns, launch)
         batch.close()
         del out
         torch.cuda.empty_cache()
@@ -400,7 +434,7 @@ def large_states(torch, I, mtgp, ctx):
         alg = G * (4 * n + 8 * N + 256)
         res[f"p{mexp}"] = {"generators": G, "numbers": G * n, "ms": round(step, 3),
                            "G_numbers_s": round(G * n / step / 1e6, 2), **roof(alg, step / 1e3),
-                           "roofline": {**roofline_block(alg, gen, step, tuning, None),
+                           "roofline": {**roofline_block(alg, gen, step, launch, None, ceilings),
                                         "avg_prepare_ms": round(median([a for a, b in times]), 4)},
                            "autotuned": tuning, "autotune_s": round(tune_s, 1)}
     return res
@@ -420,9 +454,10 @@ def large_states_wide_m(torch, I, mtgp, ctx):
     tuning = batch.autotune(rq, reps=1)
     tune_s = time.perf_counter() - t0
     plan = batch.plan(rq)
+    launch = launch_of(plan.describe())
     ms = timed_ms(torch, lambda: plan.launch(), reps=5, warmup=1)
     plan.close()
-    widths = [round_width(N, ps.pos, tuning) for ps in params]
+    widths = [round_width(N, ps.pos, launch) for ps in params]
     rounds = [-(-n // w) for w in widths]
     S = [-(-r // tuning["split_rounds"]) if tuning["split_rounds"] else 1 for r in rounds]
     seg_len = [-(-n // s) for s in S]

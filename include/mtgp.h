@@ -259,6 +259,33 @@ int mtgp_plan_launch_phase(mtgp_plan_t *p, int phase, void *stream);
 void mtgp_plan_destroy(mtgp_plan_t *p);   /* NULL-safe; waits for the batch's last stream */
 
 /*
+ * What a plan launches (for callers that report or profile it): the launch
+ * shape its generation kernel was resolved to (mode as in
+ * mtgp_batch_set_launch, never -1; for the chunked form spl is the
+ * read-ahead depth and lds_words the ring length), its work items
+ * (requests and segments), and of these the segments whose start state a
+ * jump computes. Host only. MTGP_EINVAL for NULL arguments.
+ */
+typedef struct {
+    int32_t mode;
+    uint32_t threads;
+    uint32_t spl;
+    uint32_t lds_words;
+    uint32_t grid;       /* workgroups of the generation launch */
+    uint32_t items;      /* work items of the generation launch */
+    uint32_t jumps;      /* segments started from a jump */
+} mtgp_plan_info;
+int mtgp_plan_describe(const mtgp_plan_t *p, mtgp_plan_info *info);
+
+/*
+ * The generation launch's work items in queue order: output device address
+ * and output count of item i in outs[i] and ns[i], for the first
+ * min(cap, items) items. Returns that count, or MTGP_EINVAL for NULL
+ * arguments. Host only.
+ */
+int mtgp_plan_items(const mtgp_plan_t *p, uint64_t *outs, uint64_t *ns, uint32_t cap);
+
+/*
  * Autotuner for a request list (unique generators, as for plans). Times `reps`
  * plan launches on `stream` for each candidate configuration -- the automatic
  * launch shape with no split, with the split limits of one unit's fair share

@@ -29,16 +29,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB_PATH + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
+# the store-only probe that the benchmark times beside the generation kernels
+# (a measurement aid, not part of the library)
+PROBE_PATH = os.path.join(HERE, "libmtgp_probe.so")
+PROBE_SOURCES = [os.path.join(CSRC, "store_probe.hip")]
+
+
+def _compile(sources, path, verbose):
+    tmp = path + ".tmp"
+    cmd = [HIPCC] + FLAGS + ["-o", tmp] + sources
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libmtgp.so")
-    os.replace(tmp, LIB_PATH)
+        raise RuntimeError(f"hipcc failed building {os.path.basename(path)}")
+    os.replace(tmp, path)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(SOURCES, LIB_PATH, verbose)
+    _compile(PROBE_SOURCES, PROBE_PATH, verbose)
     return LIB_PATH
 
 

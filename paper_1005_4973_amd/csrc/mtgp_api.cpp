@@ -1660,6 +1660,32 @@ int mtgp_plan_launch_phase(mtgp_plan_t *p, int phase, void *stream)
     return MTGP_OK;
 }
 
+int mtgp_plan_describe(const mtgp_plan_t *p, mtgp_plan_info *info)
+{
+    if (!p || !info)
+        return fail(MTGP_EINVAL);
+    info->mode = p->shape.mode | (p->shape.rec_basis ? kModeRecBasis : 0);
+    info->threads = (uint32_t)p->shape.threads;
+    info->spl = (uint32_t)p->shape.spl;
+    info->lds_words = (uint32_t)p->shape.lds_words;
+    info->grid = (uint32_t)p->shape.grid;
+    info->items = (uint32_t)p->items.size();
+    info->jumps = (uint32_t)p->jumps.size();
+    return MTGP_OK;
+}
+
+int mtgp_plan_items(const mtgp_plan_t *p, uint64_t *outs, uint64_t *ns, uint32_t cap)
+{
+    if (!p || (cap > 0 && (!outs || !ns)))
+        return fail(MTGP_EINVAL);
+    const uint32_t k = (uint32_t)std::min<size_t>(cap, p->items.size());
+    for (uint32_t i = 0; i < k; i++) {
+        outs[i] = p->items[i].out;
+        ns[i] = p->items[i].n;
+    }
+    return (int)k;
+}
+
 void mtgp_plan_destroy(mtgp_plan_t *p)
 {
     if (!p)

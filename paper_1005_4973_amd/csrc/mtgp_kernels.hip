@@ -25,7 +25,7 @@
 //
 // Step k of a round is done by lane k mod T in pass k / T (T = workgroup
 // size), so LDS reads and writes are unit-stride across a wavefront and the
-// outputs of a pass are one contiguous, coalesced nontemporal store.
+// outputs of a pass are one contiguous, coalesced store.
 //
 // Per step (section 3.6 and 3.7):
 //   t = x_{i+1} ^ (x_i & mask);  t ^= t << sh1;  u = t ^ (x_{i+M} >> sh2)
@@ -103,10 +103,12 @@ __device__ __forceinline__ uint32_t box_muller(uint32_t f, float shift, float tw
 // cnt outputs: the hardware range check drops the stores of slots k >= cnt,
 // so the store needs no branch (a branch lets the compiler sink the
 // tempering loads behind it) and no 64-bit address arithmetic per lane.
-// Word 3 is the gfx9-family default (32-bit data format); cache policy 2 sets
-// the nontemporal bit.
+// Word 3 is the gfx9-family default (32-bit data format). The stores are
+// plain (cache policy 0): over the output layouts of batched plans a
+// store-only kernel measured the nontemporal hint 3-5 % slower with one
+// stream per workgroup and 42 % slower with one per wavefront.
 constexpr int kBufferWord3 = 0x00020000;
-constexpr int kStoreNT = 2;
+constexpr int kStorePolicy = 0;
 
 // The window is the same for every lane of a wavefront; readfirstlane keeps
 // the descriptor in scalar registers (a descriptor in vector registers makes
@@ -205,7 +207,7 @@ __device__ __forceinline__ void round_steps(uint32_t *__restrict__ Xb, const Rec
         uint32_t o = output_word<KIND>(x[c], tv[c]);
         if constexpr (KIND == kKindNormal)
             o = box_muller(o, shift, two);   // steps k and k^1 are lanes lane and lane^1 (T is even)
-        __builtin_amdgcn_raw_buffer_store_b32(o, rsrc, (int)(k * 4u), 0, kStoreNT);
+        __builtin_amdgcn_raw_buffer_store_b32(o, rsrc, (int)(k * 4u), 0, kStorePolicy);
     }
 }
 
@@ -559,9 +561,7 @@ __device__ __forceinline__ void chunk_stream(uint32_t ringb, uint32_t rtab, uint
         uint32_t o = output_word<KIND>(x, m.t);
         if constexpr (KIND == kKindNormal)
             o = box_muller(o, shift, two);   // steps 2i and 2i+1 are lanes 2l and 2l+1 of one chunk
-        // plain stores: for many independent output streams the store-only
-        // ceiling measured 4-6 % higher than with the nontemporal hint
-        __builtin_amdgcn_raw_buffer_store_b32(o, rs, (int)(4u * lane + off), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(o, rs, (int)(4u * lane + off), 0, kStorePolicy);
     };
 
     const uint64_t Q = (n + 63) / 64;

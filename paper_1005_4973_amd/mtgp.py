@@ -64,6 +64,12 @@ class TuningC(ctypes.Structure):
                 ("split_rounds", ctypes.c_uint32), ("ms", ctypes.c_float), ("trials", ctypes.c_uint32)]
 
 
+class PlanInfoC(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("threads", ctypes.c_uint32), ("spl", ctypes.c_uint32),
+                ("lds_words", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("items", ctypes.c_uint32),
+                ("jumps", ctypes.c_uint32)]
+
+
 class RequestC(ctypes.Structure):
     _fields_ = [("gen", ctypes.c_uint32), ("kind", ctypes.c_uint32),
                 ("n", ctypes.c_uint64), ("out", ctypes.c_void_p)]
@@ -102,6 +108,8 @@ _SIGNATURES = {
     "mtgp_batch_plan_create": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.POINTER(RequestC), ctypes.c_uint32]),
     "mtgp_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mtgp_plan_launch_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "mtgp_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_plan_items": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_batch_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_server_create": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
@@ -425,6 +433,25 @@ class Plan:
         """PHASE_PREPARE (segment start states) or PHASE_GENERATE; a replay is
         both, in that order (mtgp_plan_launch_phase)."""
         _check(lib().mtgp_plan_launch_phase(self._h, int(phase), _stream_ptr(stream)), "mtgp_plan_launch_phase")
+
+    def describe(self) -> dict:
+        """The resolved launch of the generation kernel and the work item and
+        jump counts (mtgp_plan_describe)."""
+        d = PlanInfoC()
+        _check(lib().mtgp_plan_describe(self._h, ctypes.byref(d)), "mtgp_plan_describe")
+        return {f: getattr(d, f) for f, _ in PlanInfoC._fields_}
+
+    def items(self):
+        """(output device addresses, output counts) of the generation launch's
+        work items in queue order, as uint64 arrays (mtgp_plan_items)."""
+        import numpy as np
+        k = self.describe()["items"]
+        outs = np.zeros(max(k, 1), dtype=np.uint64)
+        ns = np.zeros(max(k, 1), dtype=np.uint64)
+        got = lib().mtgp_plan_items(self._h, outs.ctypes.data, ns.ctypes.data, k)
+        if got < 0:
+            raise MTGPError(got, "mtgp_plan_items")
+        return outs[:got], ns[:got]
 
     def close(self):
         if getattr(self, "_h", None):

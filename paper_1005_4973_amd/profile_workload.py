@@ -66,6 +66,11 @@ def main():
             batch.set_launch(mode, threads, spl, 0, 0)
         print(f"configuration: workload {args.workload}, split {args.split}, shape {args.shape}", flush=True)
     plan = batch.plan(rq)
+    d = plan.describe()
+    # the lines a counter summary records: what the counted launch was
+    print("split_rounds: {}".format(args.split if args.split is not None else "autotuned (see above)"), flush=True)
+    print("launch: " + " ".join(f"{k}={d[k]}" for k in ("mode", "threads", "spl", "lds_words", "grid")), flush=True)
+    print(f"work items: {d['items']}, jumps: {d['jumps']}", flush=True)
     for _ in range(3):
         plan.launch_phase(mtgp.PHASE_PREPARE)
         plan.launch_phase(mtgp.PHASE_GENERATE)
