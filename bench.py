@@ -123,8 +123,11 @@ def cpu_baseline(params, reqs, threads, passes=8):
                                    "single_stream_s": round(n1 / (m / py_s), 1)}}
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mtgp_chunk_kernel_batched_uneven_4096_traffic.md")
-TRAFFIC_PROFILE_128 = os.path.join(ROOT, "profiles", "mtgp_chunk_kernel_independent_128x4M_traffic.md")
+# committed counter summaries (profiles/*_traffic.md) per workload; a
+# launch's traffic is taken from the one recorded with the same kernel
+# sources, split limit and resolved launch
+TRAFFIC_HEADLINE = "batched_uneven_4096"
+TRAFFIC_128 = "independent_128x4M"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1005_4973_amd", "csrc", f) for f in ("mtgp_kernels.hip", "mtgp_internal.h")]
 
 
@@ -138,13 +141,25 @@ def launch_str(launch):
     return " ".join(f"{k}={launch[k]}" for k in ("mode", "threads", "spl", "lds_words", "grid"))
 
 
-def measured_traffic(launch, split_rounds, path=None):
-    """HBM bytes per launch of a generation kernel from a committed counter
-    summary, or None when the kernel sources, the split limit (which sets the
-    segments) or the resolved launch differ from those of the counter run."""
+def measured_traffic(launch, split_rounds, workload):
+    """HBM bytes per launch of a generation kernel from the committed counter
+    summaries of a workload (profiles/*_<workload>_traffic.md, or one given
+    path), or None when none of them was taken with the same kernel sources,
+    split limit (which sets the segments) and resolved launch."""
+    import glob
+    paths = [workload] if os.path.isfile(workload) else \
+        sorted(glob.glob(os.path.join(ROOT, "profiles", f"*_{workload}_traffic.md")))
+    for path in paths:
+        t = _traffic_of(path, launch, split_rounds)
+        if t is not None:
+            return t
+    return None
+
+
+def _traffic_of(path, launch, split_rounds):
     import hashlib
     try:
-        text = open(path or TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None
     h = hashlib.sha256()
@@ -194,12 +209,15 @@ def store_ceilings(torch, outs, ns, launch, fill=None):
 def phase_times(torch, plan, mtgp, stream, reps, warmup):
     """Replays of a plan as its two phases with HIP events on `stream` around
     each: per replay (prepare ms, generate ms), after `warmup` untimed
-    replays, and the wall time of the timed replays."""
+    replays. A GPU spin runs ahead of the timed replays, so that the host has
+    queued them all before the first starts: an interval then holds the
+    phase's kernels and no wait for the host's next submission."""
     for _ in range(warmup):
         plan.launch(stream)
     torch.cuda.synchronize()
     ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(reps)]
-    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(int(20e6))
     for e in ev:
         e[0].record(stream)
         plan.launch_phase(mtgp.PHASE_PREPARE, stream)
@@ -207,8 +225,21 @@ def phase_times(torch, plan, mtgp, stream, reps, warmup):
         plan.launch_phase(mtgp.PHASE_GENERATE, stream)
         e[2].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return [(a.elapsed_time(b), b.elapsed_time(c)) for a, b, c in ev], wall
+    return [(a.elapsed_time(b), b.elapsed_time(c)) for a, b, c in ev]
+
+
+def timed_steps(torch, plan, stream, steps, warmup):
+    """Wall time of `steps` whole replays (mtgp_plan_launch, one graph launch
+    each) after `warmup` untimed ones, with a device synchronisation on both
+    sides of the timed region."""
+    for _ in range(warmup):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
 
 
 def median(v):
@@ -282,7 +313,8 @@ def headline(args, torch, I, mtgp, ctx):
     plan = batch.plan(rq)
     launch = launch_of(plan.describe())
     outs, ns = plan.items()
-    times, wall = phase_times(torch, plan, mtgp, stream, args.steps, args.warmup)
+    wall = timed_steps(torch, plan, stream, args.steps, args.warmup)
+    times = phase_times(torch, plan, mtgp, stream, args.steps, 1)
     plan.close()
     prep = sum(t[0] for t in times) / len(times)
     gen = sum(t[1] for t in times) / len(times)
@@ -300,7 +332,7 @@ def headline(args, torch, I, mtgp, ctx):
                    "generators": G, "numbers_per_step": tot, "bytes_per_step": 4 * tot,
                    "autotuned": tuning, "autotune_s": round(tune_s, 1)},
         "roofline": {**roofline_block(alg, gen, wall / args.steps * 1e3, launch,
-                                      measured_traffic(launch, tuning["split_rounds"], TRAFFIC_PROFILE), ceilings),
+                                      measured_traffic(launch, tuning["split_rounds"], TRAFFIC_HEADLINE), ceilings),
                      "avg_prepare_ms": round(prep, 4)},
     }
 
@@ -327,7 +359,7 @@ def independent_128(torch, I, mtgp, ctx):
         plan = batch.plan(reqs[k])
         launch = launch_of(plan.describe())
         outs, ns = plan.items()
-        times, wall = phase_times(torch, plan, mtgp, stream, 10, 3)
+        times = phase_times(torch, plan, mtgp, stream, 10, 3)
         plan.close()
         step = median([a + b for a, b in times])
         gen = median([b for a, b in times])
@@ -336,7 +368,7 @@ def independent_128(torch, I, mtgp, ctx):
         res["kinds"][name] = {"ms": round(step, 4), "G_numbers_s": round(G * n / step / 1e6, 2),
                               "roofline": {**roofline_block(alg, gen, step, launch,
                                                             measured_traffic(launch, tuning["split_rounds"],
-                                                                             TRAFFIC_PROFILE_128)
+                                                                             TRAFFIC_128)
                                                             if k == I.KIND_U32 else None, ceilings),
                                            "avg_prepare_ms": round(median([a for a, b in times]), 4)}}
     res["G_numbers_s_three_kinds"] = round(3 * G * n / sum(steps) / 1e6, 2)
@@ -423,7 +455,7 @@ def large_states(torch, I, mtgp, ctx):
         plan = batch.plan(rq)
         launch = launch_of(plan.describe())
         outs, ns = plan.items()
-        times, wall = phase_times(torch, plan, mtgp, stream, 10, 3)
+        times = phase_times(torch, plan, mtgp, stream, 10, 3)
         plan.close()
         ceilings = store_ceilings(torch, outs, ns, launch)
         batch.close()
@@ -434,7 +466,9 @@ def large_states(torch, I, mtgp, ctx):
         alg = G * (4 * n + 8 * N + 256)
         res[f"p{mexp}"] = {"generators": G, "numbers": G * n, "ms": round(step, 3),
                            "G_numbers_s": round(G * n / step / 1e6, 2), **roof(alg, step / 1e3),
-                           "roofline": {**roofline_block(alg, gen, step, launch, None, ceilings),
+                           "roofline": {**roofline_block(alg, gen, step, launch,
+                                                         measured_traffic(launch, tuning["split_rounds"],
+                                                                          f"large_states_{mexp}"), ceilings),
                                         "avg_prepare_ms": round(median([a for a, b in times]), 4)},
                            "autotuned": tuning, "autotune_s": round(tune_s, 1)}
     return res
