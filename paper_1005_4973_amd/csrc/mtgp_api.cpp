@@ -742,8 +742,22 @@ std::vector<f2::Poly> jump_polys(const f2::Poly &psi, uint64_t J, uint32_t S)
         return h;
     const f2::Poly g = f2::powmod_x(J, psi);
     h.push_back(g);
-    for (uint32_t k = 2; k < S; k++)
-        h.push_back(f2::mulmod(h.back(), g, psi));
+    if (psi.deg < 8) {
+        for (uint32_t k = 2; k < S; k++)
+            h.push_back(f2::mulmod(h.back(), g, psi));
+        return h;
+    }
+    // h_k = h_{k-1} g in the ring of psi (table reduction)
+    f2::SquareMod ring(psi);
+    const size_t nw = ring.words();
+    std::vector<uint64_t> gw(nw, 0), cur(nw, 0), next(nw, 0);
+    std::copy(g.w.begin(), g.w.end(), gw.begin());
+    cur = gw;
+    for (uint32_t k = 2; k < S; k++) {
+        ring.mul(cur.data(), gw.data(), next.data());
+        cur.swap(next);
+        h.push_back(f2::Poly::from_words(cur.data(), (int64_t)nw * 64 - 1));
+    }
     return h;
 }
 

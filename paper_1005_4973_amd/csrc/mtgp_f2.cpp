@@ -11,7 +11,10 @@
 // of x^k.
 #include "mtgp_f2.h"
 
+#include <immintrin.h>
+
 #include <algorithm>
+#include <array>
 #include <cstring>
 
 namespace mtgp_impl {
@@ -67,9 +70,9 @@ static void xor_shl(uint64_t *dst, const uint64_t *src, size_t nsrc, int64_t shi
         dst[ws + (int64_t)nsrc] ^= carry;
 }
 
-// Carry-less product by shift-and-xor over the set bits of b (simple and
-// exact; used for all multiplications).
-static void clmul_words(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out)
+// Carry-less product by shift-and-xor over the set bits of b (the plain
+// definition; the fallback where the CPU has no carry-less multiply).
+static void clmul_words_plain(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out)
 {
     std::memset(out, 0, (na + nb + 1) * sizeof(uint64_t));
     for (size_t j = 0; j < nb; j++) {
@@ -80,6 +83,48 @@ static void clmul_words(const uint64_t *a, size_t na, const uint64_t *b, size_t 
             xor_shl(out, a, na, (int64_t)(j * 64 + t));
         }
     }
+}
+
+// The same product from 64 x 64-bit carry-less multiplications (x86
+// PCLMULQDQ): word i of a times word j of b lands in words i + j and i + j + 1.
+__attribute__((target("pclmul,sse4.1"))) static void clmul_words_pclmul(const uint64_t *a, size_t na,
+                                                                         const uint64_t *b, size_t nb,
+                                                                         uint64_t *out)
+{
+    std::memset(out, 0, (na + nb + 1) * sizeof(uint64_t));
+    for (size_t i = 0; i < na; i++) {
+        const __m128i ai = _mm_cvtsi64_si128((long long)a[i]);
+        for (size_t j = 0; j < nb; j++) {
+            const __m128i p = _mm_clmulepi64_si128(ai, _mm_cvtsi64_si128((long long)b[j]), 0x00);
+            out[i + j] ^= (uint64_t)_mm_cvtsi128_si64(p);
+            out[i + j + 1] ^= (uint64_t)_mm_extract_epi64(p, 1);
+        }
+    }
+}
+
+static bool have_pclmul()
+{
+    static const bool yes = __builtin_cpu_supports("pclmul");
+    return yes;
+}
+
+// out[0 .. na + nb] = a * b (carry-less)
+static void clmul_words(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out)
+{
+    if (have_pclmul())
+        clmul_words_pclmul(a, na, b, nb, out);
+    else
+        clmul_words_plain(a, na, b, nb, out);
+}
+
+void clmul_reference(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out)
+{
+    clmul_words_plain(a, na, b, nb, out);
+}
+
+void clmul_fast(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out)
+{
+    clmul_words(a, na, b, nb, out);
 }
 
 Poly mul(const Poly &a, const Poly &b)
@@ -170,6 +215,23 @@ Poly mulmod(const Poly &a, const Poly &b, const Poly &m) { return mod(mul(a, b),
 
 Poly powmod_x(uint64_t e, const Poly &m)
 {
+    if (m.deg >= 8) {
+        // square-and-multiply-by-x in the ring of m, squarings by table
+        SquareMod sm(m);
+        const size_t nw = sm.words();
+        std::vector<uint64_t> r(nw, 0), t(nw, 0);
+        r[0] = 1;
+        int top = 63;
+        while (top >= 0 && !((e >> top) & 1))
+            top--;
+        for (int k = top; k >= 0; k--) {
+            sm.square(r.data(), t.data());
+            r.swap(t);
+            if ((e >> k) & 1)
+                sm.times_x(r.data());
+        }
+        return Poly::from_words(r.data(), (int64_t)nw * 64 - 1);
+    }
     Poly r = Poly::one();
     if (m.deg <= 0)
         return Poly();
@@ -267,18 +329,18 @@ Poly minpoly(const uint64_t *bits, int64_t n)
 // spreads the coefficients).
 static const uint16_t *spread_table()
 {
-    static uint16_t t[256];
-    static bool init = false;
-    if (!init) {
-        for (int v = 0; v < 256; v++) {
+    // built once, thread-safely (function-local static initialisation)
+    static const std::array<uint16_t, 256> t = [] {
+        std::array<uint16_t, 256> v{};
+        for (int c = 0; c < 256; c++) {
             uint16_t s = 0;
             for (int k = 0; k < 8; k++)
-                s |= (uint16_t)(((v >> k) & 1) << (2 * k));
-            t[v] = s;
+                s |= (uint16_t)(((c >> k) & 1) << (2 * k));
+            v[(size_t)c] = s;
         }
-        init = true;
-    }
-    return t;
+        return v;
+    }();
+    return t.data();
 }
 
 SquareMod::SquareMod(const Poly &m) : D_(m.deg)
@@ -307,6 +369,7 @@ SquareMod::SquareMod(const Poly &m) : D_(m.deg)
                     xor_shl(dst, m.w.data(), m.w.size(), 8 * a + b);
         }
     work_.assign(2 * nw_ + 2 + tw_, 0);
+    m_ = m.w;
 }
 
 void SquareMod::square(const uint64_t *a, uint64_t *r)
@@ -324,6 +387,38 @@ void SquareMod::square(const uint64_t *a, uint64_t *r)
         t[2 * i] = lo;
         t[2 * i + 1] = hi;
     }
+    reduce(t);
+    std::copy(t, t + nw_, r);
+}
+
+void SquareMod::mul(const uint64_t *a, const uint64_t *b, uint64_t *r)
+{
+    uint64_t *t = work_.data();
+    std::fill(work_.begin(), work_.end(), 0);
+    clmul_words(a, nw_, b, nw_, t);   // 2 nw_ + 1 words, degree <= 2D - 2
+    reduce(t);
+    std::copy(t, t + nw_, r);
+}
+
+void SquareMod::times_x(uint64_t *a)
+{
+    // a <<= 1, then clear x^D with one multiple of m (a is reduced: only
+    // x^D can appear above degree D - 1)
+    uint64_t carry = 0;
+    for (size_t i = 0; i < nw_; i++) {
+        const uint64_t v = a[i];
+        a[i] = (v << 1) | carry;
+        carry = v >> 63;
+    }
+    const bool top = ((D_ & 63) == 0) ? carry != 0 : ((a[(size_t)(D_ >> 6)] >> (D_ & 63)) & 1) != 0;
+    if (top) {
+        for (size_t i = 0; i < m_.size() && i < nw_; i++)
+            a[i] ^= m_[i];
+    }
+}
+
+void SquareMod::reduce(uint64_t *t)
+{
     // clear the bytes above x^D, top down: byte j covers x^(D+8j) .. x^(D+8j+7)
     for (int64_t j = (D_ - 2) / 8; j >= 0; j--) {
         const int64_t e = D_ + 8 * j;
@@ -342,7 +437,6 @@ void SquareMod::square(const uint64_t *a, uint64_t *r)
         for (size_t k = 0; k < tw_; k++)
             dst[k] ^= src[k];
     }
-    std::copy(t, t + nw_, r);
 }
 
 bool irreducible_prime_degree(const Poly &m, uint32_t sieve, bool *sieved)

@@ -36,23 +36,35 @@ Poly powmod_x(uint64_t e, const Poly &m);     // x^e mod m
 // of the bit sequence s_0 .. s_{n-1}, packed like a polynomial.
 Poly minpoly(const uint64_t *bits, int64_t n);
 
-// Squaring modulo a fixed polynomial m of degree D >= 8, reduced eight
+// Arithmetic modulo a fixed polynomial m of degree D >= 8, reduced eight
 // coefficients at a time: for every value c of the byte above x^D, the
 // multiple q(c) m whose coefficients of x^D .. x^{D+7} spell c is stored
 // pre-shifted for the eight byte positions within a 64-bit word, so one
-// reduction step is one word-aligned XOR of about D/64 words.
+// reduction step is one word-aligned XOR of about D/64 words. Operands and
+// results are reduced polynomials of words() words. Not thread-safe (one
+// work buffer); build one per thread.
 class SquareMod {
 public:
     explicit SquareMod(const Poly &m);
-    size_t words() const { return nw_; }           // words of a reduced polynomial
-    void square(const uint64_t *a, uint64_t *r);   // r = a^2 mod m (a reduced, words() long)
+    size_t words() const { return nw_; }                         // words of a reduced polynomial
+    void square(const uint64_t *a, uint64_t *r);                 // r = a^2 mod m
+    void mul(const uint64_t *a, const uint64_t *b, uint64_t *r); // r = a b mod m
+    void times_x(uint64_t *a);                                   // a = x a mod m, in place
+    void reduce(uint64_t *t);   // t (2 words() + 2 words, degree <= 2D - 2) mod m, in its low words() words
 
 private:
     int64_t D_;
     size_t nw_, tw_;                 // reduced words, table entry words
     std::vector<uint64_t> table_;    // [8 alignments][256 bytes][tw_ words]
     std::vector<uint64_t> work_;     // 2 nw_ + 2 words
+    std::vector<uint64_t> m_;        // m's words
 };
+
+// Carry-less products of word arrays (out has na + nb + 1 words): the
+// shift-and-xor definition and the one the library uses (64-bit carry-less
+// multiplications where the CPU has them), for checking one against the other.
+void clmul_reference(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out);
+void clmul_fast(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out);
 
 // Irreducibility of m when its degree p is prime: m(0) = m(1) = 1, no factor
 // of degree <= sieve (gcd(m, x^(2^k) - x) = 1 for k <= sieve), and
