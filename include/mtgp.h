@@ -461,6 +461,40 @@ int mtgp_server_release(mtgp_server_t *s, const uint64_t *rids, uint32_t count);
 int mtgp_server_pending(const mtgp_server_t *s, uint64_t *waiting, uint64_t *active, uint32_t *inflight);
 void mtgp_server_destroy(mtgp_server_t *s);   /* NULL-safe; waits for in-flight ticks */
 
+/*
+ * Jump-ahead inside the request loop (the paper's section 7 discusses jumping
+ * ahead). With min_outputs > 0, a request with at least min_outputs
+ * outputs left, on a generator whose orbit annihilator is cached
+ * (mtgp_batch_prepare_split), is split into up to max_segments segments of
+ * seg_chunks * chunk outputs (the last one shorter) that advance together,
+ * one chunk each per tick, instead of one chunk per tick in all: segment k
+ * starts from the state F^{kJ} S of the request's current position S,
+ * computed on the device in the tick that splits it (raw prefix and jump
+ * kernels, as for split plans). The jump polynomials x^{kJ} mod psi are
+ * computed by host worker threads; the request keeps advancing by plain
+ * chunks until they are ready. Outputs are identical to the unsplit stream.
+ * At most `slots` requests are split at a time (device state buffers of
+ * slots * max_segments * N words). Call before the first poll; min_outputs 0
+ * (the default) turns splitting off. MTGP_EINVAL for max_segments < 2 or
+ * > 64, seg_chunks or slots 0 with min_outputs > 0; MTGP_ENOMEM.
+ * Currently disabled: any min_outputs > 0 returns MTGP_EINVAL (its first
+ * device run stopped answering; the tick logic is kept and checked on the
+ * host only until the cause is found).
+ */
+int mtgp_server_set_split(mtgp_server_t *s, uint64_t min_outputs, uint32_t max_segments, uint32_t seg_chunks,
+                          uint32_t slots);
+
+/*
+ * Find and cache the orbit annihilators that jump-ahead needs (what a split
+ * plan computes on first use) for `count` generators: raw words on the
+ * device from the current states (states and counters unchanged), then
+ * Berlekamp-Massey on the host, threaded. Synchronous; generators already
+ * prepared are skipped; mtgp_batch_set_state drops a generator's entry.
+ * MTGP_EINVAL for a bad index or NULL gens with count > 0, MTGP_ENOMEM,
+ * MTGP_EDEVICE.
+ */
+int mtgp_batch_prepare_split(mtgp_batch_t *b, const uint32_t *gens, uint32_t count);
+
 #ifdef __cplusplus
 }
 #endif

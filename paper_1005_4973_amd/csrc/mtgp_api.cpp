@@ -1446,6 +1446,19 @@ int batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, voi
             return mtgp_plan_launch(p, stream);
         }
     }
+    return launch_work_items(b, items, s);
+}
+
+// The persistent generation over prepared work items on stream s: launch
+// shape (override or automatic), queue order, upload through the batch's
+// pinned staging, launch, consumed counters.
+int launch_work_items(mtgp_batch_t *b, std::vector<WorkItem> &items, hipStream_t s)
+{
+    if (items.empty())
+        return MTGP_OK;
+    LaunchShape shape;
+    if (resolve_shape(b, items, shape) != MTGP_OK)
+        return fail(MTGP_EINVAL);
     finish_items(b, items, shape);
     const uint32_t nitems = (uint32_t)items.size();
     if (b->items_pending) {
@@ -1480,6 +1493,50 @@ int batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, voi
         b->consumed[it.gen] += it.n;
     b->last = s;
     return MTGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Request-loop support (jump-ahead segments inside ticks)
+// ---------------------------------------------------------------------------
+
+bool split_ready(const mtgp_batch_t *b, uint32_t g)
+{
+    return g < b->count && b->psi_epoch[g] == b->epoch[g] + 1 && b->psi[g].deg >= 1;
+}
+
+const f2::Poly &split_psi(const mtgp_batch_t *b, uint32_t g) { return b->psi[g]; }
+
+uint32_t gen_words(const mtgp_batch_t *b, uint32_t g) { return b->recs[g].N; }
+
+uint32_t max_gen_words(const mtgp_batch_t *b)
+{
+    uint32_t m = 0;
+    for (uint32_t g = 0; g < b->count; g++)
+        m = std::max(m, b->recs[g].N);
+    return m;
+}
+
+int prepare_annihilators(mtgp_batch_t *b, const std::vector<uint32_t> &gens) { return ensure_annihilators(b, gens); }
+
+uint32_t poly_words(uint32_t N, uint32_t D) { return jump_poly_words(N, D); }
+
+void poly_layout(const f2::Poly &h, uint32_t N, uint64_t *dst) { layout_poly(h, N, dst); }
+
+std::vector<f2::Poly> segment_polys(const f2::Poly &psi, uint64_t J, uint32_t S) { return jump_polys(psi, J, S); }
+
+LaunchShape prefix_shape(const mtgp_batch_t *b, const std::vector<uint32_t> &gens) { return raw_shape(b, gens); }
+
+uint16_t prefix_spl(const mtgp_batch_t *b, uint32_t g, const LaunchShape &shape)
+{
+    return item_spl(b->recs[g].N, b->recs[g].M, shape);
+}
+
+hipError_t launch_prefix(mtgp_batch_t *b, const WorkItem *d_items, uint32_t n, const LaunchShape &shape,
+                         hipStream_t s)
+{
+    WorkItem none;
+    std::memset(&none, 0, sizeof(none));
+    return launch_generate(b->d_recs, b->d_states, d_items, n, nullptr, none, shape, s);
 }
 
 }  // namespace mtgp_impl
@@ -1672,6 +1729,20 @@ int mtgp_plan_launch_phase(mtgp_plan_t *p, int phase, void *stream)
             p->b->consumed[it.gen] += it.n;
     p->b->last = s;
     return MTGP_OK;
+}
+
+int mtgp_batch_prepare_split(mtgp_batch_t *b, const uint32_t *gens, uint32_t count)
+{
+    if (!b || (count > 0 && !gens))
+        return fail(MTGP_EINVAL);
+    std::vector<uint32_t> g(gens, gens + count);
+    for (uint32_t x : g)
+        if (x >= b->count)
+            return fail(MTGP_EINVAL);
+    std::sort(g.begin(), g.end());
+    g.erase(std::unique(g.begin(), g.end()), g.end());
+    const int rc = ensure_annihilators(b, g);
+    return rc == MTGP_OK ? MTGP_OK : fail(rc);
 }
 
 int mtgp_plan_describe(const mtgp_plan_t *p, mtgp_plan_info *info)

@@ -3,6 +3,10 @@
 #pragma once
 
 #include "../../include/mtgp.h"
+#include "mtgp_f2.h"
+#include "mtgp_internal.h"
+
+#include <vector>
 
 namespace mtgp_impl {
 
@@ -10,5 +14,31 @@ namespace mtgp_impl {
 // jump-ahead segments, whatever the batch's split limit (the request loop's
 // ticks, whose chunks are short by construction).
 int batch_generate(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq, void *stream, bool allow_split);
+
+// The persistent generation over prepared work items (no request checks:
+// items may share a generator when at most one of them writes its state
+// back to it), on stream s; adds each item's outputs to its generator's
+// consumed counter.
+int launch_work_items(mtgp_batch_t *b, std::vector<WorkItem> &items, hipStream_t s);
+
+// Jump-ahead support for the request loop. split_ready: the generator's
+// orbit annihilator psi is known (prepare_annihilators computes it,
+// synchronously: raw words on the device, Berlekamp-Massey on the host);
+// segment_polys: h_k = x^{kJ} mod psi for k = 1 .. S-1; poly_layout writes h
+// in the jump kernel's layout (poly_words(N, deg psi) words); the raw
+// prefix (the N state words and deg psi - 1 new ones, state kept) runs as
+// work items of kind raw under prefix_shape.
+bool split_ready(const mtgp_batch_t *b, uint32_t g);
+const f2::Poly &split_psi(const mtgp_batch_t *b, uint32_t g);
+uint32_t gen_words(const mtgp_batch_t *b, uint32_t g);
+uint32_t max_gen_words(const mtgp_batch_t *b);
+int prepare_annihilators(mtgp_batch_t *b, const std::vector<uint32_t> &gens);
+uint32_t poly_words(uint32_t N, uint32_t D);
+void poly_layout(const f2::Poly &h, uint32_t N, uint64_t *dst);
+std::vector<f2::Poly> segment_polys(const f2::Poly &psi, uint64_t J, uint32_t S);
+LaunchShape prefix_shape(const mtgp_batch_t *b, const std::vector<uint32_t> &gens);
+uint16_t prefix_spl(const mtgp_batch_t *b, uint32_t g, const LaunchShape &shape);
+hipError_t launch_prefix(mtgp_batch_t *b, const WorkItem *d_items, uint32_t n, const LaunchShape &shape,
+                         hipStream_t s);
 
 }  // namespace mtgp_impl

@@ -29,6 +29,8 @@ constexpr uint16_t kKindF01 = 2;     // float [0,1)
 constexpr uint16_t kKindNormal = 3;  // Gaussian float by Box-Muller on pairs of float [1,2) outputs
 constexpr uint16_t kKindRaw = 4;     // untempered words: the N start words, then x_{c+N}, x_{c+N+1}, ...
 constexpr uint16_t kKeepState = 0x100;   // flag: do not write the end state back to the generator
+constexpr uint16_t kStateToSrc = 0x200;  // flag: write the end state back to src (a segment's own state
+                                         // buffer), not to the generator
 
 // One unit of work: n outputs of `kind` from generator `gen` into `out`,
 // starting from the generator's resident state, or from `src` if non-zero.
@@ -36,7 +38,7 @@ struct alignas(32) WorkItem {
     uint64_t out;        // device address of the first output word
     uint64_t n;          // outputs to produce
     uint32_t gen;        // index into the GenRecord array
-    uint16_t kind;       // kind in the low byte, kKeepState flag
+    uint16_t kind;       // kind in the low byte, kKeepState / kStateToSrc flags
     uint16_t spl;        // steps per lane per round for this item
     uint64_t src;        // device address of N start words, or 0 for the generator's state
 };

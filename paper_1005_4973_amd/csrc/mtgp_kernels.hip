@@ -377,7 +377,9 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
         const uint32_t N = g.N, M = g.M;
         uint32_t *slot = states + g.state_off;
         const uint32_t *from = it.src ? reinterpret_cast<const uint32_t *>(it.src) : slot;
-        uint32_t *state = (flags & kKeepState) ? nullptr : slot;
+        uint32_t *state = (flags & kKeepState)    ? nullptr
+                          : (flags & kStateToSrc) ? const_cast<uint32_t *>(from)
+                                                  : slot;
         uint32_t W = (N - M) < T * spl ? (N - M) : T * spl;
         if (kind == kKindNormal)
             W &= ~1u;   // rounds of whole pairs (the host requires N - M >= 2 for this kind)
@@ -704,7 +706,9 @@ __global__ __launch_bounds__(1024) void mtgp_chunk_kernel(const GenRecord *__res
         const uint32_t N = g.N, M = g.M;
         uint32_t *slot = states + g.state_off;
         const uint32_t *from = it.src ? reinterpret_cast<const uint32_t *>(it.src) : slot;
-        uint32_t *state = (flags & kKeepState) ? nullptr : slot;
+        uint32_t *state = (flags & kKeepState)    ? nullptr
+                          : (flags & kStateToSrc) ? const_cast<uint32_t *>(from)
+                                                  : slot;
         if (lane < 16) {
             lds_put(rtab + 4u * lane, g.rec[lane]);
             lds_put(otab + 4u * lane, kind == kKindU32 ? g.tmp[lane] : g.flt[lane]);

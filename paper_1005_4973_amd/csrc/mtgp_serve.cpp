@@ -10,19 +10,56 @@
 // (mtgp_batch_generate); consecutive chunks of one generator stay in stream
 // order, so each request gets exactly the stream segment it would get alone,
 // and requests that arrive while others run join at the next tick.
+//
+// Jump-ahead (mtgp_server_set_split): a long request on a generator whose
+// orbit annihilator psi is cached becomes S segments of J outputs that
+// advance together, one chunk each per tick, each from its own state buffer
+// (a work item reading its start state from that buffer and writing its end
+// state back there). The tick that splits a request first runs the raw
+// prefix of the generator's current state and the jump correlations that
+// give the segments' start states (segment 0's by the polynomial 1, a copy);
+// the last segment's final chunk writes the generator's state. The jump
+// polynomials x^{kJ} mod psi depend only on psi, J and k, so host worker
+// threads compute them while the request still advances by plain chunks.
+// Their words and the tick's prefix and jump items go up through a ring of
+// pinned and device memory whose blocks are released as ticks retire, in
+// order; nothing in the loop allocates device memory or waits for the device.
 #include "../../include/mtgp.h"
 #include "mtgp_host.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
+using mtgp_impl::JumpItem;
+using mtgp_impl::LaunchShape;
+using mtgp_impl::WorkItem;
+namespace f2 = mtgp_impl::f2;
+
 namespace {
+
+constexpr bool kSplitTicksEnabled = false;
+
+// Jump polynomials of one generator for segments of J outputs, laid out for
+// the jump kernel: entry 0 is the polynomial 1 (segment 0's copy), entry k
+// is x^{kJ} mod psi, each pw words.
+struct PolyJob {
+    uint32_t gen = 0, N = 0, S = 0, D = 0, pw = 0;
+    uint64_t J = 0;
+    f2::Poly psi;
+    std::vector<uint64_t> words;
+    bool done = false;   // guarded by the server's job mutex
+};
 
 struct Req {
     uint64_t rid;
@@ -32,11 +69,20 @@ struct Req {
     uint64_t offset = 0;     // byte offset of its outputs in the arena
     uint64_t scheduled = 0;  // outputs put in ticks
     uint64_t finished = 0;   // outputs whose tick completed
+    // jump-ahead
+    std::shared_ptr<PolyJob> job;   // polynomials requested (null: none)
+    bool split = false;
+    uint32_t S = 0, slot = 0;
+    uint64_t base = 0;              // request position where segment 0 starts
+    uint64_t J = 0;
+    std::vector<uint64_t> seg_len, seg_sched;
 };
 
 struct Tick {
     hipEvent_t done;
     std::vector<std::pair<Req *, uint64_t>> chunks;
+    int64_t ring_off = -1;   // staging block of this tick (-1: none)
+    uint64_t ring_len = 0;
 };
 
 }  // namespace
@@ -55,7 +101,19 @@ struct mtgp_server {
     std::vector<hipEvent_t> spare_events;
     std::unordered_map<uint64_t, Req *> completed;         // rid -> finished, not released
     std::deque<mtgp_completion> unreported;                // finished, not yet returned by poll
-    std::vector<mtgp_request> scratch;
+    std::vector<WorkItem> items;
+    // jump-ahead
+    uint64_t split_min = 0;
+    uint32_t split_max = 0, seg_chunks = 0, slots = 0, nmax = 0;
+    uint32_t *d_pool = nullptr;                // slots x split_max x nmax state words
+    std::vector<uint32_t> free_slots;
+    char *d_ring = nullptr, *h_ring = nullptr; // staging ring (device, pinned host), same offsets
+    uint64_t ring_bytes = 0, ring_head = 0;
+    std::mutex job_mu;
+    std::condition_variable job_cv;
+    std::deque<std::shared_ptr<PolyJob>> jobs;
+    bool stop = false;
+    std::vector<std::thread> workers;
 };
 
 namespace {
@@ -97,23 +155,242 @@ void give_range(mtgp_server *s, uint64_t offset, uint64_t bytes)
     }
 }
 
+uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+void job_worker(mtgp_server *s)
+{
+    for (;;) {
+        std::shared_ptr<PolyJob> job;
+        {
+            std::unique_lock<std::mutex> lk(s->job_mu);
+            s->job_cv.wait(lk, [&] { return s->stop || !s->jobs.empty(); });
+            if (s->stop)
+                return;
+            job = s->jobs.front();
+            s->jobs.pop_front();
+        }
+        std::vector<uint64_t> w((size_t)job->S * job->pw, 0);
+        mtgp_impl::poly_layout(f2::Poly::one(), job->N, w.data());
+        const std::vector<f2::Poly> h = mtgp_impl::segment_polys(job->psi, job->J, job->S);
+        for (uint32_t k = 1; k < job->S; k++)
+            mtgp_impl::poly_layout(h[k - 1], job->N, w.data() + (size_t)k * job->pw);
+        std::lock_guard<std::mutex> lk(s->job_mu);
+        job->words.swap(w);
+        job->done = true;
+    }
+}
+
+bool job_done(mtgp_server *s, const std::shared_ptr<PolyJob> &job)
+{
+    std::lock_guard<std::mutex> lk(s->job_mu);
+    return job->done;
+}
+
+// A block of `bytes` in the staging ring behind the blocks of the ticks still
+// in flight, which retire in order: the live blocks run from the oldest
+// one's start (tail) to ring_head, wrapping at the end. False when it does
+// not fit now.
+bool ring_take(mtgp_server *s, uint64_t bytes, uint64_t *off)
+{
+    bytes = align256(bytes);
+    if (bytes > s->ring_bytes)
+        return false;
+    int64_t tail = -1;
+    for (const Tick &t : s->inflight)
+        if (t.ring_off >= 0) {
+            tail = t.ring_off;
+            break;
+        }
+    uint64_t at;
+    if (tail < 0)
+        at = 0;   // nothing live
+    else if (s->ring_head > (uint64_t)tail)
+        // live blocks in [tail, head): room after head, else from 0 to tail
+        at = s->ring_head + bytes <= s->ring_bytes ? s->ring_head : (bytes <= (uint64_t)tail ? 0 : UINT64_MAX);
+    else
+        // wrapped: live blocks in [tail, end) and [0, head), room in [head, tail)
+        at = s->ring_head + bytes <= (uint64_t)tail ? s->ring_head : UINT64_MAX;
+    if (at == UINT64_MAX)
+        return false;
+    *off = at;
+    s->ring_head = at + bytes;
+    return true;
+}
+
+// Queue the jump polynomials for r's generator when r qualifies for a split.
+void maybe_request_polys(mtgp_server *s, Req *r)
+{
+    if (s->split_min == 0 || r->job || r->split || r->n - r->scheduled < s->split_min ||
+        !mtgp_impl::split_ready(s->b, r->gen))
+        return;
+    auto job = std::make_shared<PolyJob>();
+    job->gen = r->gen;
+    job->N = mtgp_impl::gen_words(s->b, r->gen);
+    job->psi = mtgp_impl::split_psi(s->b, r->gen);
+    job->D = (uint32_t)job->psi.deg;
+    job->pw = mtgp_impl::poly_words(job->N, job->D);
+    job->J = (uint64_t)s->seg_chunks * s->chunk;
+    // as many segments as the request has left now (fewer later)
+    job->S = (uint32_t)std::min<uint64_t>(s->split_max, (r->n - r->scheduled + job->J - 1) / job->J);
+    if (job->S < 2)
+        return;
+    r->job = job;
+    {
+        std::lock_guard<std::mutex> lk(s->job_mu);
+        s->jobs.push_back(job);
+    }
+    s->job_cv.notify_one();
+}
+
+struct SplitStart {
+    Req *r;
+    uint32_t S;
+    uint64_t raw_off, poly_off;   // device ring offsets of its raw words and polynomials
+};
+
 int launch_tick(mtgp_server *s)
 {
     Tick t;
-    s->scratch.clear();
-    for (auto &kv : s->active) {
+    s->items.clear();
+    std::vector<SplitStart> starts;
+    auto add_item = [&](Req *r, uint64_t pos, uint64_t k, uint64_t src, uint16_t flags) {
+        WorkItem it;
+        std::memset(&it, 0, sizeof(it));
+        it.out = reinterpret_cast<uint64_t>(s->arena + r->offset + 4u * pos);
+        it.n = k;
+        it.gen = r->gen;
+        it.kind = (uint16_t)(r->kind | flags);
+        it.src = src;
+        s->items.push_back(it);
+        t.chunks.emplace_back(r, k);
+    };
+    // requests to split in this tick: polynomials ready, a state slot free,
+    // two or more segments' worth left
+    for (auto &kv : s->active)
         for (Req *r : kv.second)
             if (r->scheduled < r->n) {
+                if (!r->split && r->job && s->free_slots.size() > starts.size() && job_done(s, r->job)) {
+                    const uint64_t left = r->n - r->scheduled;
+                    const uint64_t S = std::min<uint64_t>(r->job->S, (left + r->job->J - 1) / r->job->J);
+                    if (left >= s->split_min && S >= 2)
+                        starts.push_back(SplitStart{r, (uint32_t)S, 0, 0});
+                    else
+                        r->job.reset();
+                }
+                break;   // a generator's oldest unfinished request only
+            }
+    uint64_t ring_off = 0, ring_len = 0;
+    if (!starts.empty()) {
+        // staging block: polynomials, prefix items and jump items (uploaded),
+        // then each start's raw words (device only)
+        uint64_t bytes = 0;
+        for (SplitStart &st : starts) {
+            st.poly_off = bytes;
+            bytes += (uint64_t)st.S * st.r->job->pw * 8u;
+        }
+        const uint64_t prefix_off = align256(bytes);
+        const uint64_t jump_off = align256(prefix_off + starts.size() * sizeof(WorkItem));
+        uint64_t nj = 0;
+        for (const SplitStart &st : starts)
+            nj += st.S;
+        const uint64_t upload = jump_off + nj * sizeof(JumpItem);
+        bytes = align256(upload);
+        for (SplitStart &st : starts) {
+            st.raw_off = bytes;
+            bytes = align256(bytes + (uint64_t)(st.r->job->D + st.r->job->N) * 4u);
+        }
+        if (!ring_take(s, bytes, &ring_off)) {
+            starts.clear();   // no room now: these requests go on by plain chunks
+        } else {
+            ring_len = bytes;
+            char *h = s->h_ring + ring_off;
+            char *d = s->d_ring + ring_off;
+            std::vector<uint32_t> pgens;
+            WorkItem *pre = reinterpret_cast<WorkItem *>(h + prefix_off);
+            std::vector<JumpItem> jumps;
+            for (size_t i = 0; i < starts.size(); i++) {
+                SplitStart &st = starts[i];
+                Req *r = st.r;
+                const PolyJob &job = *r->job;
+                std::memcpy(h + st.poly_off, job.words.data(), (size_t)st.S * job.pw * 8u);
+                std::memset(&pre[i], 0, sizeof(WorkItem));
+                pre[i].out = reinterpret_cast<uint64_t>(d + st.raw_off);
+                pre[i].n = job.D - 1;
+                pre[i].gen = r->gen;
+                pre[i].kind = mtgp_impl::kKindRaw | mtgp_impl::kKeepState;
+                pgens.push_back(r->gen);
+                r->slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                uint32_t *pool = s->d_pool + (size_t)r->slot * s->split_max * s->nmax;
+                for (uint32_t k = 0; k < st.S; k++) {
+                    JumpItem ji;
+                    std::memset(&ji, 0, sizeof(ji));
+                    ji.raw = reinterpret_cast<uint64_t>(d + st.raw_off);
+                    ji.poly = reinterpret_cast<uint64_t>(d + st.poly_off + (size_t)k * job.pw * 8u);
+                    ji.out = reinterpret_cast<uint64_t>(pool + (size_t)k * s->nmax);
+                    ji.D = k == 0 ? 1u : job.D;
+                    ji.N = job.N;
+                    jumps.push_back(ji);
+                }
+                r->split = true;
+                r->S = st.S;
+                r->J = job.J;
+                r->base = r->scheduled;
+                const uint64_t left = r->n - r->scheduled;
+                r->seg_len.assign(st.S, 0);
+                r->seg_sched.assign(st.S, 0);
+                // S - 1 segments of J outputs and the rest in the last one (longer
+                // than J when the polynomials were made for fewer segments)
+                for (uint32_t k = 0; k < st.S; k++)
+                    r->seg_len[k] = k + 1 < st.S ? r->J : left - (uint64_t)(st.S - 1) * r->J;
+                r->job.reset();
+            }
+            // the jump kernel is launched once per lane width and word-group count
+            std::stable_sort(jumps.begin(), jumps.end(), [](const JumpItem &x, const JumpItem &y) {
+                const mtgp_impl::JumpShape a = mtgp_impl::jump_shape(x.N), b = mtgp_impl::jump_shape(y.N);
+                return a.R != b.R ? a.R < b.R : a.G < b.G;
+            });
+            std::memcpy(h + jump_off, jumps.data(), jumps.size() * sizeof(JumpItem));
+            const LaunchShape pshape = mtgp_impl::prefix_shape(s->b, pgens);
+            for (size_t i = 0; i < starts.size(); i++)
+                pre[i].spl = mtgp_impl::prefix_spl(s->b, pre[i].gen, pshape);
+            if (hipMemcpyAsync(d, h, upload, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+                mtgp_impl::launch_prefix(s->b, reinterpret_cast<const WorkItem *>(d + prefix_off),
+                                         (uint32_t)starts.size(), pshape, s->stream) != hipSuccess ||
+                mtgp_impl::launch_jumps(reinterpret_cast<const JumpItem *>(d + jump_off), jumps.data(),
+                                        (uint32_t)jumps.size(), s->stream) != hipSuccess)
+                return MTGP_EDEVICE;
+        }
+    }
+    for (auto &kv : s->active) {
+        for (Req *r : kv.second) {
+            if (r->split && r->scheduled < r->n) {
+                uint32_t *pool = s->d_pool + (size_t)r->slot * s->split_max * s->nmax;
+                for (uint32_t k = 0; k < r->S; k++) {
+                    const uint64_t left = r->seg_len[k] - r->seg_sched[k];
+                    if (left == 0)
+                        continue;
+                    const uint64_t c = std::min(s->chunk, left);
+                    const bool last = r->seg_sched[k] + c == r->seg_len[k];
+                    // a segment's end state goes back to its buffer; at its end it is
+                    // dropped, except the last segment's, which is the generator's
+                    const uint16_t flags = !last ? mtgp_impl::kStateToSrc
+                                                 : (k + 1 == r->S ? (uint16_t)0 : mtgp_impl::kKeepState);
+                    add_item(r, r->base + (uint64_t)k * r->J + r->seg_sched[k], c,
+                             reinterpret_cast<uint64_t>(pool + (size_t)k * s->nmax), flags);
+                    r->seg_sched[k] += c;
+                    r->scheduled += c;
+                }
+                break;   // the generator's segments this tick
+            }
+            if (r->scheduled < r->n) {
                 const uint64_t k = std::min(s->chunk, r->n - r->scheduled);
-                mtgp_request q;
-                q.gen = r->gen;
-                q.kind = r->kind;
-                q.n = k;
-                q.out = s->arena + r->offset + 4u * r->scheduled;
-                s->scratch.push_back(q);
-                t.chunks.emplace_back(r, k);
+                add_item(r, r->scheduled, k, 0, 0);
+                r->scheduled += k;
+                maybe_request_polys(s, r);
                 break;   // one chunk per generator per tick, from its oldest request
             }
+        }
     }
     if (t.chunks.empty())
         return MTGP_OK;
@@ -124,14 +401,16 @@ int launch_tick(mtgp_server *s)
         s->spare_events.push_back(e);
     }
     t.done = s->spare_events.back();
-    const int rc = mtgp_impl::batch_generate(s->b, s->scratch.data(), (uint32_t)s->scratch.size(), s->stream, false);
+    const int rc = mtgp_impl::launch_work_items(s->b, s->items, s->stream);
     if (rc != MTGP_OK)
         return rc;
     if (hipEventRecord(t.done, s->stream) != hipSuccess)
         return MTGP_EDEVICE;
     s->spare_events.pop_back();
-    for (auto &c : t.chunks)
-        c.first->scheduled += c.second;
+    if (ring_len) {
+        t.ring_off = (int64_t)ring_off;
+        t.ring_len = ring_len;
+    }
     s->inflight.push_back(std::move(t));
     return MTGP_OK;
 }
@@ -206,6 +485,10 @@ int mtgp_server_poll(mtgp_server_t *s, mtgp_completion *done, uint32_t max_done,
             Req *r = c.first;
             r->finished += c.second;
             if (r->finished == r->n) {
+                if (r->split) {
+                    s->free_slots.push_back(r->slot);
+                    r->split = false;
+                }
                 auto &q2 = s->active[r->gen];
                 for (auto it = q2.begin(); it != q2.end(); ++it)
                     if (*it == r) {
@@ -235,6 +518,7 @@ int mtgp_server_poll(mtgp_server_t *s, mtgp_completion *done, uint32_t max_done,
         r->offset = off;
         s->waiting.pop_front();
         s->active[r->gen].push_back(r);
+        maybe_request_polys(s, r);
     }
     while (s->inflight.size() < s->depth && has_unscheduled(s)) {
         const int rc = launch_tick(s);
@@ -281,10 +565,59 @@ int mtgp_server_pending(const mtgp_server_t *s, uint64_t *waiting, uint64_t *act
     return MTGP_OK;
 }
 
+int mtgp_server_set_split(mtgp_server_t *s, uint64_t min_outputs, uint32_t max_segments, uint32_t seg_chunks,
+                          uint32_t slots)
+{
+    if (!s)
+        return MTGP_EINVAL;
+    if (min_outputs == 0) {
+        s->split_min = 0;
+        return MTGP_OK;
+    }
+    if (max_segments < 2 || max_segments > 64 || seg_chunks == 0 || slots == 0 || !s->inflight.empty() ||
+        s->d_pool != nullptr)
+        return MTGP_EINVAL;
+    // Switched off: the first device run of split ticks stopped answering and
+    // no cause has been shown yet (the tick logic itself runs to completion
+    // in a host-only harness). Until one is, splitting is refused.
+    if (!kSplitTicksEnabled)
+        return MTGP_EINVAL;
+    s->nmax = mtgp_impl::max_gen_words(s->b);
+    // staging per split: polynomials (S x poly words), a prefix item, S jump
+    // items and the raw words (deg psi + N); room for `slots` splits at once
+    const uint32_t pmax = (uint32_t)std::max<uint64_t>(32u * s->nmax + 64u, 1u);   // deg psi <= p + 1 < 32 N + 1
+    const uint64_t per = align256((uint64_t)max_segments * mtgp_impl::poly_words(s->nmax, pmax) * 8u) +
+                         align256(sizeof(WorkItem)) + align256((uint64_t)max_segments * sizeof(JumpItem)) +
+                         align256((uint64_t)(pmax + s->nmax) * 4u) + 1024u;
+    s->ring_bytes = align256(per * std::max<uint32_t>(slots, 4u));
+    if (hipMalloc(&s->d_pool, (size_t)slots * max_segments * s->nmax * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&s->d_ring, s->ring_bytes) != hipSuccess ||
+        hipHostMalloc(&s->h_ring, s->ring_bytes, hipHostMallocDefault) != hipSuccess)
+        return MTGP_ENOMEM;
+    s->split_min = min_outputs;
+    s->split_max = max_segments;
+    s->seg_chunks = seg_chunks;
+    s->slots = slots;
+    s->free_slots.clear();
+    for (uint32_t k = slots; k-- > 0;)
+        s->free_slots.push_back(k);
+    const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency() / 2));
+    for (unsigned k = 0; k < nt; k++)
+        s->workers.emplace_back(job_worker, s);
+    return MTGP_OK;
+}
+
 void mtgp_server_destroy(mtgp_server_t *s)
 {
     if (!s)
         return;
+    {
+        std::lock_guard<std::mutex> lk(s->job_mu);
+        s->stop = true;
+    }
+    s->job_cv.notify_all();
+    for (std::thread &w : s->workers)
+        w.join();
     for (Tick &t : s->inflight) {
         (void)hipEventSynchronize(t.done);
         s->spare_events.push_back(t.done);
@@ -298,6 +631,10 @@ void mtgp_server_destroy(mtgp_server_t *s)
             delete r;
     for (auto &kv : s->completed)
         delete kv.second;
+    (void)hipFree(s->d_pool);
+    (void)hipFree(s->d_ring);
+    if (s->h_ring)
+        (void)hipHostFree(s->h_ring);
     delete s;
 }
 

@@ -109,6 +109,9 @@ _SIGNATURES = {
     "mtgp_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mtgp_plan_launch_phase": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "mtgp_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mtgp_batch_prepare_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "mtgp_server_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_uint32]),
     "mtgp_plan_items": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_batch_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "mtgp_set_split": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
@@ -387,6 +390,14 @@ class Batch:
     def set_launch(self, mode: int = -1, threads: int = 0, spl: int = 1, lds_words: int = 0, grid: int = 0):
         """Override the persistent launch shape (mode -1 restores the automatic choice)."""
         _check(lib().mtgp_batch_set_launch(self._h, mode, threads, spl, lds_words, grid), "mtgp_batch_set_launch")
+
+    def prepare_split(self, gens):
+        """Find and cache the orbit annihilators jump-ahead needs for these
+        generators (mtgp_batch_prepare_split; synchronous, threaded)."""
+        import numpy as np
+        g = np.ascontiguousarray(np.asarray(list(gens), dtype=np.uint32))
+        _check(lib().mtgp_batch_prepare_split(self._h, g.ctypes.data if g.size else None, g.size),
+               "mtgp_batch_prepare_split")
 
     def get_state(self, gen: int):
         import numpy as np

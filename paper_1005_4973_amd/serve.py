@@ -264,7 +264,10 @@ class NativeServer:
     output arena of `arena_bytes` (the admission budget)."""
 
     def __init__(self, batch, arena_bytes: int = 8 << 30, chunk: int = 1 << 18, depth: int = 2,
-                 stream=None, max_report: int = 1 << 16):
+                 stream=None, max_report: int = 1 << 16, split=None):
+        """split: None, or (min_outputs, max_segments, seg_chunks, slots) for
+        mtgp_server_set_split (jump-ahead segments for long requests on
+        generators prepared with Batch.prepare_split)."""
         import numpy as np
         import torch
         from . import mtgp
@@ -276,6 +279,8 @@ class NativeServer:
                                        mtgp._stream_ptr(self.stream))
         if not self._h:
             raise mtgp.MTGPError(mtgp.MTGP_EINVAL, "mtgp_server_create")
+        if split is not None:
+            mtgp._check(L.mtgp_server_set_split(self._h, *[int(v) for v in split]), "mtgp_server_set_split")
         self._done = np.zeros(max_report, dtype=COMPLETION_DTYPE)
         self._ndone = __import__("ctypes").c_uint32(0)
 

@@ -102,3 +102,68 @@ def test_native_server_alone_vs_mix(env):
     srv2.close()
     srv.close()
     b.close()
+
+
+@pytest.mark.skip(reason="split ticks are switched off in the library (mtgp_server_set_split refuses them): "
+                         "the first device run of this test stopped answering and no cause has been shown yet")
+def test_native_server_split_alone_vs_mix(env):
+    """Jump-ahead inside the request loop: requests above the split limit on
+    prepared generators run as concurrent segments (started in whatever tick
+    their polynomials are ready, so some first advance by plain chunks),
+    beside short requests, requests of unprepared generators and normals.
+    Every request gets the oracle's stream segment for its generator in
+    arrival order, and the generators end in the oracle's states."""
+    torch, mtgp, serve = env
+    G = 64
+    params = I.draw_param_sets([11213] * 40 + [23209] * 16 + [44497] * 8, 5500)
+    seeds = I.state_seeds(G)
+    rng = I.SplitMix64(5501)
+    trace, t = [], 0.0
+    for i in range(400):
+        t += 2e-5
+        g = rng.uniform_int(0, G - 1) if i % 4 else rng.uniform_int(0, 11)
+        if i % 9 == 0:
+            n = rng.uniform_int(200_000, 600_000)        # above the split limit
+        else:
+            n = rng.uniform_int(1, 20_000)
+        k = 3 if i % 7 == 0 else rng.uniform_int(0, 2)
+        if k == 3:
+            n += n & 1
+        trace.append((t, g, n, k))
+    # long requests on generators 0..47 can split; 48..63 have no annihilator
+    b = mtgp.Batch(params, seeds)
+    b.prepare_split(range(48))
+    chunk = 1 << 14
+    say(f"split server trace: {len(trace)} requests, {sum(1 for x in trace if x[2] >= 200_000)} long")
+    srv = serve.NativeServer(b, arena_bytes=64 << 20, chunk=chunk, depth=2, split=(1 << 16, 8, 2, 16))
+    got = {}
+    st = srv.run(trace, realtime=True, on_complete=lambda rid, out: got.__setitem__(rid, bits(out)))
+    assert st.completed == len(trace) and len(got) == len(trace)
+    assert srv.pending() == (0, 0, 0)
+    srv.close()
+    states = {}
+    for rid, (_, g, n, k) in enumerate(trace):
+        assert got[rid].size == n
+        st_g = states.setdefault(g, O.seed_state(seeds[g], params[g].mexp))
+        if k == 3:
+            z = got[rid].view(np.float32).astype(np.float64)
+            assert np.abs(z - O.normals(params[g], st_g, n)).max() <= 1.5e-5, f"rid={rid}"
+        else:
+            np.testing.assert_array_equal(got[rid], O.generate(params[g], st_g, n, k), err_msg=f"rid={rid} g={g}")
+    for g, st_g in states.items():
+        words, consumed = b.get_state(g)
+        np.testing.assert_array_equal(words, st_g, err_msg=f"end state g={g}")
+        assert consumed == sum(n for (_, gg, n, _) in trace if gg == g)
+    # the same generators alone: one long request each, served by a fresh server
+    b2 = mtgp.Batch(params, seeds)
+    b2.prepare_split([0, 41, 60])
+    srv2 = serve.NativeServer(b2, arena_bytes=16 << 20, chunk=chunk, depth=2, split=(1 << 16, 8, 2, 4))
+    got2 = {}
+    alone = [(0.0, 0, 333_334, 0), (0.0, 41, 300_000, 1), (0.0, 60, 250_000, 2)]
+    srv2.run(alone, realtime=False, on_complete=lambda rid, out: got2.__setitem__(rid, bits(out)))
+    srv2.close()
+    for rid, (_, g, n, k) in enumerate(alone):
+        np.testing.assert_array_equal(got2[rid], O.generate(params[g], O.seed_state(seeds[g], params[g].mexp), n, k),
+                                      err_msg=f"alone g={g}")
+    b2.close()
+    b.close()
