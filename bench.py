@@ -571,51 +571,63 @@ def single_stream(torch, I, mtgp, ctx):
 
 def serving(torch, I, mtgp, ctx):
     """65536 resident MTGP-11213 states served by the library's request loop
-    (mtgp_server_*, native admission and tick building; Python only feeds
-    arrivals): saturation rate with all requests available at once, then
-    Poisson arrivals at fractions of it. One point with the Python loop
-    (serve.Server) is kept for comparison."""
+    (mtgp_server_*: native admission and tick building; Python only releases
+    arrivals on time and collects completions). Capacity: the completion
+    rate of an open-loop burst offered well above it. Sweep: open-loop
+    Poisson arrivals at fractions of that capacity, each point at least 2 s
+    and 10^4 requests, log-normal sizes (median 2^16, sigma 1.5, clipped to
+    [2^10, 2^26]): p50/p99 latency, sustained requests/s and numbers/s (and
+    their share of 8 TB/s); the knee is the first load whose p99 is at least
+    5x the p99 at load 0.1 (the sweep stops one point after it)."""
     from paper_1005_4973_amd import serve
     G = 65536
     params = I.serving_params(G)
     batch = mtgp.Batch(params, I.state_seeds(G))
     arena, chunk = 8 << 30, 1 << 18
 
-    def native(trace, realtime):
+    def native(trace, realtime=True):
         srv = serve.NativeServer(batch, arena_bytes=arena, chunk=chunk, depth=2)
         st = srv.run(trace, realtime=realtime)
         srv.close()
         return st
 
-    def point(load, st, lam=None, num=None):
-        d = {"load": load, "req_per_s": round(lam if lam is not None else st.completed / st.wall_s, 1),
-             "completed": st.completed, "numbers_per_s": round(st.numbers / st.wall_s, 1),
-             "p50_ms": round(st.percentile(50) * 1e3, 3), "p99_ms": round(st.percentile(99) * 1e3, 3)}
-        if num is not None:
-            d["requests"] = num
-        return d
+    def point(load, st, lam, num):
+        return {"load": load, "offered_req_per_s": round(lam, 1), "requests": num, "completed": st.completed,
+                "wall_s": round(st.wall_s, 3), "req_per_s": round(st.completed / st.wall_s, 1),
+                "numbers_per_s": round(st.numbers / st.wall_s, 1),
+                "frac_of_8TBs": round(4 * st.numbers / st.wall_s / 1e12 / 8.0, 4),
+                "p50_ms": round(float(st.percentile(50)) * 1e3, 3), "p99_ms": round(float(st.percentile(99)) * 1e3, 3)}
 
-    sat_trace = I.serving_trace(20000, rate_per_s=1.0, num_gens=G, seed=5001)
-    native(sat_trace[:500], False)          # warm-up
-    st = native(sat_trace, False)
-    sat_rate = st.completed / st.wall_s
-    points = [point("saturation", st)]
-    for frac in (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
-        lam = frac * sat_rate
-        num = int(min(40000, max(500, lam * 1.5)))
-        trace = I.serving_trace(num, rate_per_s=lam, num_gens=G, seed=6000 + int(frac * 100))
-        s = native(trace, True)
-        points.append(point(frac, s, lam, num))
+    native(I.serving_trace_arrays(2000, 1e5, G, seed=5000), True)        # warm-up
+    # capacity: an open-loop burst offered at 4M requests/s for 0.5 s
+    burst = I.serving_trace_arrays(2_000_000, 4e6, G, seed=5001)
+    st = native(burst, True)
+    cap = st.completed / st.wall_s
+    log(f"serving capacity estimate: {cap:.0f} requests/s ({st.numbers / st.wall_s / 1e9:.1f} G numbers/s)")
+    points = []
+    after_knee = 0
+    for frac in (0.1, 0.25, 0.5, 0.75, 1.0, 1.15, 1.3, 1.5, 1.75, 2.0):
+        lam = frac * cap
+        num = int(max(10_000, lam * 2.0))
+        trace = I.serving_trace_arrays(num, lam, G, seed=6000 + int(frac * 100))
+        points.append(point(frac, native(trace, True), lam, num))
         log(f"serving load {frac}: {points[-1]}")
-    # the Python loop at the rate the native loop sustained at 0.5 load, for comparison
-    lam = 0.5 * sat_rate
-    trace = I.serving_trace(int(min(12000, max(500, lam * 1.5))), rate_per_s=lam, num_gens=G, seed=6050)
-    srv = serve.Server(serve.GpuExecutor(batch), mem_budget_bytes=arena, chunk=chunk, depth=2, keep_outputs=False)
-    py = point(0.5, srv.run(trace, realtime=True), lam, len(trace))
+        if points[-1]["p99_ms"] >= 5 * points[0]["p99_ms"]:
+            after_knee += 1
+            if after_knee == 2:
+                break   # past the knee: further points only queue longer
+    base = points[0]["p99_ms"]
+    knee = next((p["load"] for p in points if p["p99_ms"] >= 5 * base), None)
+    at = next((p for p in points if p["load"] == knee), None)
     batch.close()
     torch.cuda.empty_cache()
     return {"generators": G, "chunk": chunk, "arena_GiB": arena >> 30, "sigma": 1.5, "loop": "native",
-            "points": points, "python_loop_at_0.5": py}
+            "capacity_req_per_s": round(cap, 1), "points": points,
+            "knee": {"load": knee, "p99_ms": at["p99_ms"] if at else None,
+                     "sustained_numbers_per_s": at["numbers_per_s"] if at else None,
+                     "frac_of_8TBs": at["frac_of_8TBs"] if at else None,
+                     "rule": "first load with p99 >= 5 x p99 at load 0.1"},
+            "split_ticks": "off (mtgp_server_set_split refuses them for now)"}
 
 
 def main():

@@ -95,6 +95,7 @@ struct mtgp_server {
     uint32_t depth = 0;
     hipStream_t stream = nullptr;
     std::map<uint64_t, uint64_t> free_ranges;              // offset -> length, disjoint and coalesced
+    std::multimap<uint64_t, uint64_t> free_by_size;        // length -> offset, the same ranges
     std::deque<Req *> waiting;                             // submitted, not admitted
     std::unordered_map<uint32_t, std::deque<Req *>> active;    // generator -> admitted, unfinished
     std::deque<Tick> inflight;
@@ -122,19 +123,32 @@ constexpr uint64_t kAlign = 256;   // output regions start on 256-byte boundarie
 
 uint64_t round_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+void size_erase(mtgp_server *s, uint64_t offset, uint64_t length)
+{
+    auto range = s->free_by_size.equal_range(length);
+    for (auto it = range.first; it != range.second; ++it)
+        if (it->second == offset) {
+            s->free_by_size.erase(it);
+            return;
+        }
+}
+
+// Best fit: the smallest free range that holds `bytes` (ties: any), found
+// through the length index in O(log ranges).
 bool take_range(mtgp_server *s, uint64_t bytes, uint64_t *offset)
 {
-    for (auto it = s->free_ranges.begin(); it != s->free_ranges.end(); ++it)
-        if (it->second >= bytes) {
-            *offset = it->first;
-            const uint64_t rest = it->second - bytes;
-            const uint64_t at = it->first + bytes;
-            s->free_ranges.erase(it);
-            if (rest)
-                s->free_ranges.emplace(at, rest);
-            return true;
-        }
-    return false;
+    auto it = s->free_by_size.lower_bound(bytes);
+    if (it == s->free_by_size.end())
+        return false;
+    const uint64_t at = it->second, len = it->first;
+    s->free_by_size.erase(it);
+    s->free_ranges.erase(at);
+    *offset = at;
+    if (len > bytes) {
+        s->free_ranges.emplace(at + bytes, len - bytes);
+        s->free_by_size.emplace(len - bytes, at + bytes);
+    }
+    return true;
 }
 
 void give_range(mtgp_server *s, uint64_t offset, uint64_t bytes)
@@ -143,16 +157,20 @@ void give_range(mtgp_server *s, uint64_t offset, uint64_t bytes)
     // merge with the following and the preceding range
     auto next = std::next(it);
     if (next != s->free_ranges.end() && it->first + it->second == next->first) {
+        size_erase(s, next->first, next->second);
         it->second += next->second;
         s->free_ranges.erase(next);
     }
     if (it != s->free_ranges.begin()) {
         auto prev = std::prev(it);
         if (prev->first + prev->second == it->first) {
+            size_erase(s, prev->first, prev->second);
             prev->second += it->second;
             s->free_ranges.erase(it);
+            it = prev;
         }
     }
+    s->free_by_size.emplace(it->second, it->first);
 }
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
@@ -446,6 +464,7 @@ mtgp_server_t *mtgp_server_create(mtgp_batch_t *b, void *arena, uint64_t arena_b
     s->depth = depth;
     s->stream = static_cast<hipStream_t>(stream);
     s->free_ranges.emplace(0, s->arena_bytes);
+    s->free_by_size.emplace(s->arena_bytes, 0);
     return s;
 }
 

@@ -231,6 +231,20 @@ def serving_trace(num_requests: int, rate_per_s: float, num_gens: int = 65536, s
     return out
 
 
+def serving_trace_arrays(num_requests: int, rate_per_s: float, num_gens: int = 65536, seed: int = 5001,
+                         median_log2: int = 16, sigma: float = 1.5, lo_log2: int = 10, hi_log2: int = 26):
+    """The serving_trace distributions drawn with numpy (PCG64 seeded by
+    `seed`) for long traces: arrays (arrival s, gen, n, kind)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.cumsum(rng.exponential(1.0 / rate_per_s, num_requests))
+    n = np.rint((2.0 ** median_log2) * np.exp(sigma * rng.standard_normal(num_requests))).astype(np.int64)
+    n = np.clip(n, 1 << lo_log2, 1 << hi_log2)
+    v = rng.integers(0, 4, num_requests)
+    kind = np.where(v < 2, KIND_U32, np.where(v == 2, KIND_F12, KIND_F01))
+    gen = rng.integers(0, num_gens, num_requests)
+    return t, gen, n, kind
+
+
 def serving_params(num_gens: int = 65536) -> List[ParamSet]:
     return draw_param_sets([11213] * num_gens, 5000, M_POLICY_PAPER)
 

@@ -325,20 +325,28 @@ class NativeServer:
         self.kept maps rid -> (offset, n) and the caller releases them; a trace
         whose kept outputs outgrow the arena raises instead of waiting)."""
         np = self.np
-        arrival = np.array([t[0] if realtime else 0.0 for t in trace], dtype=np.float64)
-        reqs = np.zeros(len(trace), dtype=SERVER_REQUEST_DTYPE)
-        reqs["rid"] = np.arange(len(trace))
-        reqs["gen"] = [t[1] for t in trace]
-        reqs["n"] = [t[2] for t in trace]
-        reqs["kind"] = [t[3] for t in trace]
-        t_done = np.full(len(trace), np.nan)
+        if isinstance(trace, tuple) and len(trace) == 4 and hasattr(trace[0], "shape"):
+            t_in, g_in, n_in, k_in = trace          # arrays (inputs.serving_trace_arrays)
+        else:
+            t_in = [t[0] for t in trace]
+            g_in = [t[1] for t in trace]
+            n_in = [t[2] for t in trace]
+            k_in = [t[3] for t in trace]
+        count = len(t_in)
+        arrival = np.asarray(t_in, dtype=np.float64) if realtime else np.zeros(count)
+        reqs = np.zeros(count, dtype=SERVER_REQUEST_DTYPE)
+        reqs["rid"] = np.arange(count)
+        reqs["gen"] = g_in
+        reqs["n"] = n_in
+        reqs["kind"] = k_in
+        t_done = np.full(count, np.nan)
         self.kept = {}
         t0 = clock()
         i = 0
         outstanding = 0
-        while i < len(trace) or outstanding > 0:
+        while i < count or outstanding > 0:
             now = clock() - t0
-            j = int(np.searchsorted(arrival, now, side="right")) if realtime else len(trace)
+            j = int(np.searchsorted(arrival, now, side="right")) if realtime else count
             if j > i:
                 self.submit(reqs[i:j])
                 outstanding += j - i
@@ -361,13 +369,13 @@ class NativeServer:
                     if waiting and not active and not inflight:
                         raise RuntimeError("the arena is full of kept outputs: release some or use a larger arena")
                 time.sleep(poll_s)                            # work on the device: poll again shortly
-            elif i < len(trace):
+            elif i < count:
                 time.sleep(max(0.0, arrival[i] - (clock() - t0)))   # idle until the next arrival
         wall = clock() - t0
         ok = ~np.isnan(t_done)
         lat = list((t_done - arrival)[ok])
-        span = trace[-1][0] if (realtime and trace) else 0.0
-        rate = len(trace) / span if span > 0 else math.inf
+        span = float(arrival[-1]) if (realtime and count) else 0.0
+        rate = count / span if span > 0 else math.inf
         return ServeStats(rate, int(ok.sum()), 0, int(reqs["n"][ok].sum()), wall, lat)
 
     def close(self):
