@@ -72,13 +72,14 @@ typedef struct {
 
 /* The row vector (b_0 b_1 b_2 b_3) of the four LSBs of v, written most
  * significant first (b_0 = bit 3 of v, b_3 = bit 0), times the matrix:
- * the XOR of the rows j with b_j = 1 (sections 3.6 and 3.7). */
+ * the XOR of the rows j with b_j = 1 (sections 3.6 and 3.7). Each row is
+ * taken through the mask 0 - b_j (all ones when b_j = 1, zero otherwise),
+ * so the selection needs no branch on the data. */
 static uint32_t orc_vec4_times(uint32_t v, const orc_mat4 *a)
 {
     uint32_t acc = 0;
     for (int j = 0; j < 4; j++)
-        if ((v >> (3 - j)) & 1u)
-            acc ^= a->row[j];
+        acc ^= a->row[j] & (0u - ((v >> (3 - j)) & 1u));
     return acc;
 }
 
