@@ -624,3 +624,53 @@ def test_eager_batch_calls_split(M):
         np.testing.assert_array_equal(words, states[g])
         assert consumed == sum(n for n, _ in calls)
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# A searched, paper-shaped production-size set (section 5): sh1 = 13, sh2 = 4,
+# an ID embedded in R, period 2^11213 - 1. The library's seeded host search
+# produces it at test time (the same seed as the slow search test, whose
+# oracle run pins its full period by Berlekamp-Massey and the irreducibility
+# test); nothing is stored. The GPU's outputs are compared with the oracle's.
+# ---------------------------------------------------------------------------
+
+def test_searched_full_period_11213_set(M):
+    import torch
+    found, stats = M.search_params(11213, id=1, seed=11213)
+    ps = I.ParamSet(found.mexp, found.pos, found.sh1, found.sh2, tuple(found.param_tbl), tuple(found.temper_tbl))
+    say(f"searched set: M={ps.pos} sh1={ps.sh1} sh2={ps.sh2} after {stats['draws']} draws")
+    assert (ps.sh1, ps.sh2) == (13, 4) and ps.param_tbl[8] >> 16 == 0 and (ps.param_tbl[4] >> 4) & 0xFFFF == 1
+    # a batch of 64 states of the one set (the deployment the paper describes:
+    # one parameter set per block of work, many seeds), every kind, ragged
+    # lengths, then a split plan over the continued streams
+    G = 64
+    seeds = [11213 + 7 * g for g in range(G)]
+    params = [ps] * G
+    b = M.Batch(params, seeds)
+    states = {g: O.seed_state(seeds[g], ps.mexp) for g in range(G)}
+    rng = I.SplitMix64(11214)
+    reqs = []
+    for g in range(G):
+        k = g % 4
+        n = rng.uniform_int(1, 70000)
+        reqs.append((g, k, n + (n & 1) if k == 3 else n))
+    bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+    b.generate([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+    torch.cuda.synchronize()
+    for (g, k, n), buf in zip(reqs, bufs):
+        if k == 3:
+            assert np.abs(host_f32(buf) - O.normals(ps, states[g], n)).max() <= NORMAL_ATOL, f"gen={g}"
+        else:
+            np.testing.assert_array_equal(host_bits(buf), O.generate(ps, states[g], n, k), err_msg=f"gen={g} kind={k}")
+    b.set_split(64)
+    reqs = [(g, g % 3, 200_000 + 997 * g) for g in range(8)]
+    bufs = [torch.empty(n, dtype=torch.int32, device="cuda") for (_, _, n) in reqs]
+    plan = b.plan([(g, k, n, buf) for (g, k, n), buf in zip(reqs, bufs)])
+    plan.launch()
+    torch.cuda.synchronize()
+    plan.close()
+    for (g, k, n), buf in zip(reqs, bufs):
+        np.testing.assert_array_equal(host_bits(buf), O.generate(ps, states[g], n, k), err_msg=f"split gen={g}")
+    for g in range(G):
+        np.testing.assert_array_equal(b.get_state(g)[0], states[g], err_msg=f"end state gen={g}")
+    b.close()
