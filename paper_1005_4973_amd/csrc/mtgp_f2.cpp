@@ -102,6 +102,25 @@ __attribute__((target("pclmul,sse4.1"))) static void clmul_words_pclmul(const ui
     }
 }
 
+// n x n words -> 2n words, column by column: word k collects the low halves
+// of the products a_i b_j with i + j = k and the high halves of those with
+// i + j = k - 1, accumulated in a 128-bit register.
+__attribute__((target("pclmul,sse4.1"))) static void clmul_square_pclmul(const uint64_t *a, const uint64_t *b,
+                                                                          size_t n, uint64_t *out)
+{
+    __m128i carry = _mm_setzero_si128();
+    for (size_t k = 0; k + 1 < 2 * n; k++) {
+        __m128i acc = carry;
+        const size_t i0 = k < n ? 0 : k - n + 1, i1 = k < n ? k : n - 1;
+        for (size_t i = i0; i <= i1; i++)
+            acc = _mm_xor_si128(acc, _mm_clmulepi64_si128(_mm_cvtsi64_si128((long long)a[i]),
+                                                          _mm_cvtsi64_si128((long long)b[k - i]), 0x00));
+        out[k] = (uint64_t)_mm_cvtsi128_si64(acc);
+        carry = _mm_srli_si128(acc, 8);
+    }
+    out[2 * n - 1] = (uint64_t)_mm_cvtsi128_si64(carry);
+}
+
 static bool have_pclmul()
 {
     static const bool yes = __builtin_cpu_supports("pclmul");
@@ -115,6 +134,49 @@ static void clmul_words(const uint64_t *a, size_t na, const uint64_t *b, size_t 
         clmul_words_pclmul(a, na, b, nb, out);
     else
         clmul_words_plain(a, na, b, nb, out);
+}
+
+// Karatsuba (A. Karatsuba and Yu. Ofman, 1962) over 64-bit words:
+// out[0 .. 2n) = a * b for n-word a and b, from three half-size products per
+// level; below kKaraBase words the word-by-word product above. ws holds at
+// least kara_scratch(n) words.
+constexpr size_t kKaraBase = 16;
+
+static size_t kara_scratch(size_t n) { return 4 * n + 8 * 64; }
+
+static void clmul_kara(const uint64_t *a, const uint64_t *b, size_t n, uint64_t *out, uint64_t *ws)
+{
+    if (n <= kKaraBase) {
+        if (have_pclmul()) {
+            clmul_square_pclmul(a, b, n, out);
+        } else {
+            uint64_t tmp[2 * kKaraBase + 1];
+            clmul_words_plain(a, n, b, n, tmp);   // its top word is zero
+            std::copy(tmp, tmp + 2 * n, out);
+        }
+        return;
+    }
+    const size_t h = n / 2, hh = n - h;   // low and high halves, hh >= h
+    clmul_kara(a, b, h, out, ws);                      // a_lo b_lo -> out[0, 2h)
+    clmul_kara(a + h, b + h, hh, out + 2 * h, ws);     // a_hi b_hi -> out[2h, 2n)
+    uint64_t *as = ws, *bs = ws + hh, *z1 = ws + 2 * hh;
+    for (size_t i = 0; i < hh; i++) {
+        as[i] = a[h + i] ^ (i < h ? a[i] : 0);
+        bs[i] = b[h + i] ^ (i < h ? b[i] : 0);
+    }
+    clmul_kara(as, bs, hh, z1, ws + 4 * hh);           // (a_lo + a_hi)(b_lo + b_hi)
+    for (size_t i = 0; i < 2 * h; i++)
+        z1[i] ^= out[i];
+    for (size_t i = 0; i < 2 * hh; i++)
+        z1[i] ^= out[2 * h + i];
+    for (size_t i = 0; i < 2 * hh; i++)                // middle term at word h
+        out[h + i] ^= z1[i];
+}
+
+void clmul_karatsuba(const uint64_t *a, const uint64_t *b, size_t n, uint64_t *out)
+{
+    std::vector<uint64_t> ws(kara_scratch(n));
+    clmul_kara(a, b, n, out, ws.data());
 }
 
 void clmul_reference(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out)
@@ -347,6 +409,24 @@ SquareMod::SquareMod(const Poly &m) : D_(m.deg)
 {
     spread_table();
     nw_ = (size_t)((D_ + 63) / 64);
+    m_ = m.w;
+    if (D_ >= kBarrettMinDegree) {
+        // mu = floor(x^(2D) / m), degree D; m and mu padded to nw_ + 1 words
+        Poly x2d;
+        x2d.w.assign((size_t)(2 * D_ / 64 + 1), 0);
+        x2d.w[(size_t)(2 * D_ >> 6)] = 1ull << ((2 * D_) & 63);
+        x2d.deg = 2 * D_;
+        const Poly mu = divide(x2d, m, nullptr);
+        const size_t n1 = nw_ + 1;
+        mu_.assign(n1, 0);
+        std::copy(mu.w.begin(), mu.w.end(), mu_.begin());
+        mpad_.assign(n1, 0);
+        std::copy(m.w.begin(), m.w.end(), mpad_.begin());
+        bar_.assign(6 * n1 + kara_scratch(n1), 0);
+        tw_ = 0;
+        work_.assign(2 * nw_ + 2, 0);
+        return;
+    }
     tw_ = (size_t)((D_ + 8 + 56) / 64 + 1);
     // q(c): the byte q with bits D .. D+7 of q m equal to c
     std::vector<uint8_t> q_of(256, 0);
@@ -369,7 +449,6 @@ SquareMod::SquareMod(const Poly &m) : D_(m.deg)
                     xor_shl(dst, m.w.data(), m.w.size(), 8 * a + b);
         }
     work_.assign(2 * nw_ + 2 + tw_, 0);
-    m_ = m.w;
 }
 
 void SquareMod::square(const uint64_t *a, uint64_t *r)
@@ -395,7 +474,10 @@ void SquareMod::mul(const uint64_t *a, const uint64_t *b, uint64_t *r)
 {
     uint64_t *t = work_.data();
     std::fill(work_.begin(), work_.end(), 0);
-    clmul_words(a, nw_, b, nw_, t);   // 2 nw_ + 1 words, degree <= 2D - 2
+    if (!mu_.empty())
+        clmul_kara(a, b, nw_, t, bar_.data());   // 2 nw_ words, degree <= 2D - 2
+    else
+        clmul_words(a, nw_, b, nw_, t);          // 2 nw_ + 1 words
     reduce(t);
     std::copy(t, t + nw_, r);
 }
@@ -417,8 +499,36 @@ void SquareMod::times_x(uint64_t *a)
     }
 }
 
+// dst[0 .. nd) = (src >> shift) for src of ns words (zero beyond)
+static void shr_words(const uint64_t *src, size_t ns, int64_t shift, uint64_t *dst, size_t nd)
+{
+    const size_t ws = (size_t)(shift >> 6);
+    const int bs = (int)(shift & 63);
+    for (size_t i = 0; i < nd; i++) {
+        const size_t k = ws + i;
+        uint64_t v = k < ns ? src[k] >> bs : 0;
+        if (bs && k + 1 < ns)
+            v |= src[k + 1] << (64 - bs);
+        dst[i] = v;
+    }
+}
+
 void SquareMod::reduce(uint64_t *t)
 {
+    if (!mu_.empty()) {
+        // Barrett reduction over F2[x] (P. Barrett, 1986): for deg t <= 2D - 1
+        // the quotient floor(t / m) is exactly floor(floor(t / x^D) mu / x^D),
+        // with no correction step, so t mod m = t + q m in the low D bits
+        const size_t n1 = nw_ + 1;
+        uint64_t *th = bar_.data(), *p1 = th + n1, *q = p1 + 2 * n1, *p2 = q + n1, *ws = p2 + 2 * n1;
+        shr_words(t, 2 * nw_ + 1, D_, th, n1);
+        clmul_kara(th, mu_.data(), n1, p1, ws);
+        shr_words(p1, 2 * n1, D_, q, n1);
+        clmul_kara(q, mpad_.data(), n1, p2, ws);
+        for (size_t i = 0; i < nw_; i++)
+            t[i] ^= p2[i];
+        return;
+    }
     // clear the bytes above x^D, top down: byte j covers x^(D+8j) .. x^(D+8j+7)
     for (int64_t j = (D_ - 2) / 8; j >= 0; j--) {
         const int64_t e = D_ + 8 * j;

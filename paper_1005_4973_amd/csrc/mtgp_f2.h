@@ -36,13 +36,19 @@ Poly powmod_x(uint64_t e, const Poly &m);     // x^e mod m
 // of the bit sequence s_0 .. s_{n-1}, packed like a polynomial.
 Poly minpoly(const uint64_t *bits, int64_t n);
 
-// Arithmetic modulo a fixed polynomial m of degree D >= 8, reduced eight
+// Arithmetic modulo a fixed polynomial m of degree D >= 8. From
+// kBarrettMinDegree on, the reduction is Barrett's with Karatsuba products
+// (two products of about D/64-word operands per reduction); below it, eight
 // coefficients at a time: for every value c of the byte above x^D, the
 // multiple q(c) m whose coefficients of x^D .. x^{D+7} spell c is stored
 // pre-shifted for the eight byte positions within a 64-bit word, so one
-// reduction step is one word-aligned XOR of about D/64 words. Operands and
-// results are reduced polynomials of words() words. Not thread-safe (one
+// reduction step is one word-aligned XOR. (That table holds 2048 entries of
+// D/64 words: at the generators' degrees it no longer fits in cache, and
+// Barrett's form measured 4x to 19x faster from D = 521 to 44497.) Operands
+// and results are reduced polynomials of words() words. Not thread-safe (one
 // work buffer); build one per thread.
+constexpr int64_t kBarrettMinDegree = 64;
+
 class SquareMod {
 public:
     explicit SquareMod(const Poly &m);
@@ -58,6 +64,9 @@ private:
     std::vector<uint64_t> table_;    // [8 alignments][256 bytes][tw_ words]
     std::vector<uint64_t> work_;     // 2 nw_ + 2 words
     std::vector<uint64_t> m_;        // m's words
+    std::vector<uint64_t> mu_;       // Barrett: floor(x^(2D) / m), nw_ + 1 words (empty: table reduction)
+    std::vector<uint64_t> mpad_;     // Barrett: m in nw_ + 1 words
+    std::vector<uint64_t> bar_;      // Barrett: products and Karatsuba scratch
 };
 
 // Carry-less products of word arrays (out has na + nb + 1 words): the
@@ -65,6 +74,8 @@ private:
 // multiplications where the CPU has them), for checking one against the other.
 void clmul_reference(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out);
 void clmul_fast(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint64_t *out);
+// The Karatsuba form for two n-word operands (out has 2n words).
+void clmul_karatsuba(const uint64_t *a, const uint64_t *b, size_t n, uint64_t *out);
 
 // Irreducibility of m when its degree p is prime: m(0) = m(1) = 1, no factor
 // of degree <= sieve (gcd(m, x^(2^k) - x) = 1 for k <= sieve), and

@@ -6,6 +6,7 @@
 #include "../../include/mtgp.h"
 #include "../../paper_1005_4973_amd/csrc/mtgp_f2.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -62,12 +63,26 @@ static void test_clmul()
             clmul_fast(a.data(), na, b.data(), nb, r2.data());
             CHECK(r1 == r2, "clmul %zu x %zu words", na, nb);
         }
+    // Karatsuba against the shift-and-xor definition, around its base size
+    // and through odd splits
+    for (size_t n : {1u, 2u, 15u, 16u, 17u, 31u, 33u, 65u, 100u, 364u}) {
+        std::vector<uint64_t> a(n), b(n), r1(2 * n + 1), r2(2 * n);
+        for (auto &w : a)
+            w = next64();
+        for (auto &w : b)
+            w = next64();
+        clmul_reference(a.data(), n, b.data(), n, r1.data());
+        clmul_karatsuba(a.data(), b.data(), n, r2.data());
+        CHECK(r1[2 * n] == 0 && std::equal(r2.begin(), r2.end(), r1.begin()), "karatsuba %zu words", n);
+    }
 }
 
 // ring operations against the plain definitions (mod of the plain product)
 static void test_ring()
 {
-    for (int64_t D : {8, 63, 64, 65, 127, 128, 521, 2203, 11213, 11214}) {
+    // table reduction below 64, Barrett from 64 on (64, 128, 4096 and 11264
+    // are word multiples)
+    for (int64_t D : {8, 63, 64, 65, 127, 128, 521, 2203, 4095, 4096, 4097, 11213, 11214, 11264, 23209}) {
         const Poly m = random_poly(D);
         SquareMod ring(m);
         const size_t nw = ring.words();
