@@ -374,7 +374,7 @@ const char *mtgp_strerror(int code);
  * above the four LSBs are taken) -- the four LSBs of the rows drawn until
  * I + R44 is invertible, the remaining bits random. A candidate is accepted
  * when the minimal polynomial (Berlekamp-Massey) of bit 31 of its raw words
- * has degree mexp and is irreducible (no factor of degree <= 28, and
+ * has degree mexp and is irreducible (no factor of degree <= 256, and
  * x^(2^mexp) = x modulo it): for a Mersenne exponent mexp that means period
  * 2^mexp - 1. The tempering table is a random F2-linear table (its
  * equidistribution search needs SIS and is not done). Candidate i uses a
@@ -389,7 +389,7 @@ typedef struct {
     uint64_t draws;          /* index of the accepted candidate + 1 (max_draws if none) */
     uint64_t evaluated;      /* candidates evaluated by all threads */
     uint64_t full_degree;    /* of those, linear complexity mexp */
-    uint64_t sieve_passed;   /* of those, no factor of degree <= 28 */
+    uint64_t sieve_passed;   /* of those, no factor of degree <= 256 */
     double seconds;          /* wall time */
 } mtgp_search_stats;
 int mtgp_search_params(uint32_t mexp, uint32_t id, uint64_t seed, uint64_t max_draws, uint32_t threads,

@@ -43,7 +43,7 @@ struct SplitMix64 {
 };
 
 constexpr uint32_t kSh1 = 13, kSh2 = 4;
-constexpr uint32_t kSieve = 28;   // reject factors of degree <= 28 before the full test
+constexpr uint32_t kSieve = 256;   // reject factors of degree <= 256 before the full test
 
 struct Candidate {
     uint32_t M;

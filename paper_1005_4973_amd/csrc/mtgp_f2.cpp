@@ -563,20 +563,35 @@ bool irreducible_prime_degree(const Poly &m, uint32_t sieve, bool *sieved)
         return false;   // m(1) = 0: x + 1 divides m
     SquareMod sm(m);
     const size_t nw = sm.words();
-    std::vector<uint64_t> r(nw, 0), t(nw, 0);
-    r[0] = 2;   // x
+    std::vector<uint64_t> r(nw, 0), t(nw, 0), acc(nw, 0), d(nw, 0);
+    r[0] = 2;     // x
+    acc[0] = 1;   // product of x^(2^k) - x since the last check
+    // An irreducible factor of degree j divides x^(2^k) - x exactly when j
+    // divides k. For k < p (p prime) an irreducible m has no such factor, so
+    // the sieve stops below p. The terms are multiplied together and checked
+    // with one gcd at k = 2, 4, 8, ... and at the sieve's end: m shares a
+    // factor with the product iff it shares one with a term.
+    const int64_t last = std::min<int64_t>(sieve, p - 1);
+    int64_t check = 2;
     for (int64_t k = 1; k <= p; k++) {
         sm.square(r.data(), t.data());
         r.swap(t);
-        if ((uint32_t)k <= sieve) {
-            // gcd(m, x^(2^k) - x) = 1, else m has a factor of degree dividing k
-            Poly g;
-            g.w = r;
-            g.w[0] ^= 2;
-            g.trim();
-            if (g.deg >= 0 && gcd(m, g).deg > 0)
-                return false;
-            if ((uint32_t)k == sieve && sieved)
+        if (k <= last) {
+            d = r;
+            d[0] ^= 2;
+            sm.mul(acc.data(), d.data(), t.data());
+            acc.swap(t);
+            if (k == check || k == last) {
+                Poly g;
+                g.w = acc;
+                g.trim();
+                if (gcd(m, g).deg > 0)   // (g = 0: m divides the product)
+                    return false;
+                std::fill(acc.begin(), acc.end(), 0);
+                acc[0] = 1;
+                check *= 2;
+            }
+            if (k == last && sieved)
                 *sieved = true;
         }
     }

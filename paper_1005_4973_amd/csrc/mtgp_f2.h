@@ -78,7 +78,8 @@ void clmul_fast(const uint64_t *a, size_t na, const uint64_t *b, size_t nb, uint
 void clmul_karatsuba(const uint64_t *a, const uint64_t *b, size_t n, uint64_t *out);
 
 // Irreducibility of m when its degree p is prime: m(0) = m(1) = 1, no factor
-// of degree <= sieve (gcd(m, x^(2^k) - x) = 1 for k <= sieve), and
+// of degree <= min(sieve, p - 1) (gcd(m, x^(2^k) - x) = 1 for those k, a
+// filter that rejects most reducible m before the full test), and
 // x^(2^p) = x mod m. *sieved is set when the sieve passed.
 bool irreducible_prime_degree(const Poly &m, uint32_t sieve, bool *sieved);
 

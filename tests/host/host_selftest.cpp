@@ -148,6 +148,38 @@ static void test_minpoly()
     red.w[0] ^= 2;   // x^89 + x^38 + x + 1 has the root 1
     red.trim();
     CHECK(!irreducible_prime_degree(red, 10, &sieved), "reducible rejected");
+
+    // against trial division by every polynomial of degree <= 8, for random
+    // polynomials of the prime degree 17 (the sieve reaches p - 1 = 16 with
+    // sieve 256, only 4 with sieve 4, none with 0)
+    int irreducible = 0;
+    for (int trial = 0; trial < 3000; trial++) {
+        Poly m;
+        m.w = {(next64() & 0x1ffffull) | (1ull << 17) | 1ull};
+        m.trim();
+        bool divisible = false;
+        for (uint64_t dv = 2; dv < 512 && !divisible; dv++) {
+            Poly dp;
+            dp.w = {dv};
+            dp.trim();
+            Poly rem;
+            divide(m, dp, &rem);
+            divisible = rem.deg < 0;
+        }
+        for (uint32_t sv : {0u, 4u, 256u}) {
+            const bool irr = irreducible_prime_degree(m, sv, nullptr);
+            CHECK(irr == !divisible, "degree 17 poly %llx sieve %u", (unsigned long long)m.w[0], sv);
+        }
+        irreducible += !divisible;
+    }
+    CHECK(irreducible > 50, "degree 17: %d irreducible of 3000", irreducible);
+    // the sieve only rejects: the same decisions at degree 89 without it
+    for (int trial = 0; trial < 400; trial++) {
+        Poly m = random_poly(89);
+        m.w[0] |= 1;
+        CHECK(irreducible_prime_degree(m, 0, nullptr) == irreducible_prime_degree(m, 256, nullptr),
+              "degree 89 sieve 0 vs 256");
+    }
 }
 
 static void test_search_and_equidistribution()
