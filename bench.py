@@ -216,13 +216,17 @@ def phase_times(torch, plan, mtgp, stream, reps, warmup):
     each: per replay (prepare ms, generate ms), after `warmup` untimed
     replays. A GPU spin runs ahead of the timed replays, so that the host has
     queued them all before the first starts: an interval then holds the
-    phase's kernels and no wait for the host's next submission."""
+    phase's kernels and no wait for the host's next submission. Untimed
+    replays queued behind the spin run right before the timed ones, so the
+    timed ones follow busy work, not the idle spin."""
     for _ in range(warmup):
         plan.launch(stream)
     torch.cuda.synchronize()
     ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(reps)]
     with torch.cuda.stream(stream):
         torch.cuda._sleep(int(20e6))
+    for _ in range(max(warmup, 10)):
+        plan.launch(stream)
     for e in ev:
         e[0].record(stream)
         plan.launch_phase(mtgp.PHASE_PREPARE, stream)

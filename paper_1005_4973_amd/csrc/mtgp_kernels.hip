@@ -446,17 +446,18 @@ __global__ __launch_bounds__(1024) void mtgp_kernel(const GenRecord *__restrict_
 // taken 64 at a time in a software pipeline instead of all at once behind a
 // barrier.
 //
-// The state lives in a ring of L words (L a power of two, L >= N + 64): x_p
-// sits in slot p mod L. A chunk reads slots a .. a + M with a = (64q + lane)
-// mod L, i.e. up to M - 1 slots past the ring's end, so every new word is
-// written twice, at its slot and L slots on (one two-address LDS write), and
-// the reads never wrap. No compaction copy is needed. (Writing the second
-// copy only for the chunks that need it takes a branch per chunk, after which
-// the compiler waits for every outstanding LDS operation and the pipeline
-// drains.) LDS per wavefront: 2L ring words at a multiple of 2L words, so a
-// slot's byte address is (4 slot) & (4L - 1) | ring base; after all rings,
-// each wavefront's 16-word recursion table and 16-word output table, each at
-// a multiple of 64 bytes, so a lookup's address is (4 index) | table base.
+// The state lives in a ring of L words (L a power of two, L >= N + 64): the
+// new word x_{N+j} sits in slot j mod L, the start words x_k (k < N) in slots
+// L - N + k, and every word is stored twice, at its slot and L slots on (two
+// LDS writes). The words step j reads, x_j .. x_{j+M}, are then found at
+// slots (j mod L) + L - N .. (j mod L) + L - N + M, all below 2L: the reads
+// never wrap and no compaction copy is needed. (Writing the second copy only
+// for the chunks that need it takes a branch per chunk, after which the
+// compiler waits for every outstanding LDS operation and the pipeline
+// drains.) LDS per wavefront: 2L ring words at a multiple of 2L words; after
+// all rings, each wavefront's 16-word recursion table and 16-word output
+// table, each at a multiple of 64 bytes, so a lookup's address is
+// (4 index) | table base.
 // ---------------------------------------------------------------------------
 
 typedef __attribute__((address_space(3))) uint32_t lds_word;

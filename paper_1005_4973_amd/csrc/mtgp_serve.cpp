@@ -1,8 +1,10 @@
 // Continuous-batching request loop over a batch's resident generators.
 //
 // Requests (generator, kind, n) are queued by the caller and admitted in
-// arrival order while their outputs fit the output arena (first fit; a
-// request that does not fit waits, and so do the ones behind it). Every
+// arrival order while their outputs fit the output arena (best fit: the
+// smallest free range that holds the request, found through an index of the
+// free ranges by length; a request that does not fit waits, and so do the
+// ones behind it). Every
 // scheduling step retires ticks whose completion event has fired, admits
 // what fits, and launches ticks while fewer than `depth` are in flight. A
 // tick advances every generator that has admitted work by up to `chunk`
@@ -11,19 +13,20 @@
 // order, so each request gets exactly the stream segment it would get alone,
 // and requests that arrive while others run join at the next tick.
 //
-// Jump-ahead (mtgp_server_set_split): a long request on a generator whose
-// orbit annihilator psi is cached becomes S segments of J outputs that
-// advance together, one chunk each per tick, each from its own state buffer
-// (a work item reading its start state from that buffer and writing its end
-// state back there). The tick that splits a request first runs the raw
-// prefix of the generator's current state and the jump correlations that
-// give the segments' start states (segment 0's by the polynomial 1, a copy);
-// the last segment's final chunk writes the generator's state. The jump
-// polynomials x^{kJ} mod psi depend only on psi, J and k, so host worker
-// threads compute them while the request still advances by plain chunks.
-// Their words and the tick's prefix and jump items go up through a ring of
-// pinned and device memory whose blocks are released as ticks retire, in
-// order; nothing in the loop allocates device memory or waits for the device.
+// Jump-ahead (mtgp_server_set_split; refused for now, see kSplitTicksEnabled):
+// a long request on a generator whose orbit annihilator psi is cached becomes
+// S segments of J outputs that advance together, one chunk each per tick, each
+// from its own state buffer (a work item reading its start state from that
+// buffer and writing its end state back there). The tick that splits a request
+// first runs the raw prefix of the generator's current state and the jump
+// correlations that give the segments' start states (segment 0's by the
+// polynomial 1, a copy); the last segment's final chunk writes the generator's
+// state. The jump polynomials x^{kJ} mod psi depend only on psi, J and k, so
+// host worker threads compute them while the request still advances by plain
+// chunks. Their words and the tick's prefix and jump items go up through a
+// ring of pinned and device memory whose blocks are released as ticks retire,
+// in order; nothing in the loop allocates device memory or waits for the
+// device.
 #include "../../include/mtgp.h"
 #include "mtgp_host.h"
 

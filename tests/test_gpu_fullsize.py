@@ -1,9 +1,9 @@
 """Parity at the workloads' full sizes, in the configurations the benchmark
-times: autotuned jump-ahead plans for the 128 x 2^22 headline, the 256 x
-2^24 large-state batches (under the paper's M rule and the wide one) and the
-4096-request uneven batch (every output of every generator, copied back in
-chunks), and the native request loop over 65536 states (every request). The
-oracle runs on host threads (its C calls release the GIL).
+times: autotuned jump-ahead plans for the 4096-request uneven batch (the
+headline; every output of two replays, copied back in chunks), the 128 x 2^22
+batch, the 256 x 2^24 large-state batches (under the paper's M rule and the
+wide one), and the native request loop over 65536 states (every request).
+The oracle runs on host threads (its C calls release the GIL).
 """
 import os
 from concurrent.futures import ThreadPoolExecutor
@@ -41,7 +41,7 @@ def device_words(out, start, n):
 
 
 @pytest.mark.timeout(600)
-def test_headline_tuned_plans_full_size(M):
+def test_independent_128_tuned_plans_full_size(M):
     """128 MTGP-11213 generators x 2^22 as uint32, float [1,2), float [0,1):
     the tuned split plans, replayed twice; all outputs compared."""
     import torch
@@ -53,7 +53,7 @@ def test_headline_tuned_plans_full_size(M):
     outs = {k: torch.empty(G * n, dtype=torch.int32, device="cuda") for k in kinds}
     reqs = {k: [(g, k, n, outs[k].data_ptr() + 4 * g * n) for g in range(G)] for k in kinds}
     tuning = b.autotune(reqs[I.KIND_U32], reps=2)
-    say(f"headline tuning {tuning}")
+    say(f"128 x 2^22 tuning {tuning}")
     plans = [b.plan(reqs[k]) for k in kinds]
     states = [O.seed_state(seeds[g], params[g].mexp) for g in range(G)]
     for rep in range(2):
@@ -149,8 +149,10 @@ def test_large_states_wide_m_full_size(M):
 @pytest.mark.timeout(900)
 def test_batched_uneven_full_size(M):
     """4096 requests, exponents 2:1:1, lengths log-uniform in [2^10, 2^24],
-    mixed kinds, autotuned persistent plan: every request's outputs compared
-    (copied back about 1 GiB at a time), and every final state."""
+    mixed kinds, autotuned persistent plan replayed twice (the second replay's
+    segments start from jumps over the states the first one left): every
+    request's outputs compared after each replay (copied back about 1 GiB at
+    a time), and every final state."""
     import torch
     params, reqs = I.batched_uneven()
     G = len(params)
@@ -162,8 +164,6 @@ def test_batched_uneven_full_size(M):
     tuning = b.autotune(rq, reps=1)
     say(f"uneven tuning {tuning}")
     plan = b.plan(rq)
-    plan.launch()
-    torch.cuda.synchronize()
     states = {g: O.seed_state(seeds[g], params[g].mexp) for g in range(G)}
     # requests are packed in order: compare them in groups of about 2^28 outputs
     groups, cur, size = [], [], 0
@@ -175,15 +175,19 @@ def test_batched_uneven_full_size(M):
             cur, size = [], 0
     if cur:
         groups.append(cur)
-    with pool() as ex:
-        for grp in groups:
-            base = grp[0].offset
-            host = device_words(out, base, grp[-1].offset + grp[-1].n - base)
-            refs = list(ex.map(lambda r: O.generate(params[r.gen], states[r.gen], r.n, r.kind), grp))
-            for r, want in zip(grp, refs):
-                np.testing.assert_array_equal(host[r.offset - base:r.offset - base + r.n], want,
-                                              err_msg=f"gen={r.gen} mexp={params[r.gen].mexp} n={r.n} kind={r.kind}")
-    say(f"uneven: all {len(reqs)} requests equal")
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        with pool() as ex:
+            for grp in groups:
+                base = grp[0].offset
+                host = device_words(out, base, grp[-1].offset + grp[-1].n - base)
+                refs = list(ex.map(lambda r: O.generate(params[r.gen], states[r.gen], r.n, r.kind), grp))
+                for r, want in zip(grp, refs):
+                    np.testing.assert_array_equal(
+                        host[r.offset - base:r.offset - base + r.n], want,
+                        err_msg=f"rep={rep} gen={r.gen} mexp={params[r.gen].mexp} n={r.n} kind={r.kind}")
+        say(f"uneven replay {rep}: all {len(reqs)} requests equal")
     for g in range(G):
         np.testing.assert_array_equal(b.get_state(g)[0], states[g], err_msg=f"state gen={g}")
     plan.close()
