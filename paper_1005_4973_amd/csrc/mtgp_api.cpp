@@ -482,15 +482,23 @@ std::vector<WorkItem> items_of(const mtgp_request *reqs, uint32_t nreq)
 // (rounds = ceil(n / W), each round weighted by its slots per lane).
 void finish_items(const mtgp_batch *b, std::vector<WorkItem> &items, const LaunchShape &s)
 {
-    for (WorkItem &it : items)
-        it.spl = item_spl(b->recs[it.gen].N, b->recs[it.gen].M, s);
-    auto cost = [&](const WorkItem &it) {
+    // each item's cost once, then the items in decreasing cost, equal costs
+    // in their given order
+    std::vector<std::pair<uint64_t, uint32_t>> key(items.size());
+    for (size_t i = 0; i < items.size(); i++) {
+        WorkItem &it = items[i];
         const GenRecord &r = b->recs[it.gen];
+        it.spl = item_spl(r.N, r.M, s);
         const uint64_t w = round_width(r.N, r.M, s);
-        return (it.n + w - 1) / w * (uint64_t)it.spl;
-    };
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const WorkItem &x, const WorkItem &y) { return cost(x) > cost(y); });
+        key[i] = {(it.n + w - 1) / w * (uint64_t)it.spl, (uint32_t)i};
+    }
+    std::sort(key.begin(), key.end(), [](const std::pair<uint64_t, uint32_t> &x, const std::pair<uint64_t, uint32_t> &y) {
+        return x.first != y.first ? x.first > y.first : x.second < y.second;
+    });
+    std::vector<WorkItem> sorted(items.size());
+    for (size_t i = 0; i < key.size(); i++)
+        sorted[i] = items[key[i].second];
+    items.swap(sorted);
 }
 
 void batch_free(mtgp_batch *b)

@@ -40,6 +40,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -69,6 +70,7 @@ struct Req {
     uint32_t gen;
     uint32_t kind;
     uint64_t n;
+    Req *next = nullptr;     // the generator's next admitted request
     uint64_t offset = 0;     // byte offset of its outputs in the arena
     uint64_t scheduled = 0;  // outputs put in ticks
     uint64_t finished = 0;   // outputs whose tick completed
@@ -79,6 +81,14 @@ struct Req {
     uint64_t base = 0;              // request position where segment 0 starts
     uint64_t J = 0;
     std::vector<uint64_t> seg_len, seg_sched;
+};
+
+// A generator's admitted, unfinished requests in arrival order (an intrusive
+// list), and the oldest of them with outputs not yet put in a tick.
+struct GenQ {
+    Req *head = nullptr, *tail = nullptr;
+    Req *sched = nullptr;
+    bool ready = false;   // listed in the server's ready generators
 };
 
 struct Tick {
@@ -98,9 +108,12 @@ struct mtgp_server {
     uint32_t depth = 0;
     hipStream_t stream = nullptr;
     std::map<uint64_t, uint64_t> free_ranges;              // offset -> length, disjoint and coalesced
-    std::multimap<uint64_t, uint64_t> free_by_size;        // length -> offset, the same ranges
+    std::set<std::pair<uint64_t, uint64_t>> free_by_size;  // (length, offset) of the same ranges
     std::deque<Req *> waiting;                             // submitted, not admitted
-    std::unordered_map<uint32_t, std::deque<Req *>> active;    // generator -> admitted, unfinished
+    std::vector<GenQ> gq;                                  // per generator: admitted, unfinished
+    std::vector<uint32_t> ready, ready_next;               // generators with outputs to put in ticks
+    uint64_t active = 0;                                   // admitted, unfinished requests
+    std::vector<Req *> req_pool;                           // released requests, for reuse
     std::deque<Tick> inflight;
     std::vector<hipEvent_t> spare_events;
     std::unordered_map<uint64_t, Req *> completed;         // rid -> finished, not released
@@ -126,24 +139,16 @@ constexpr uint64_t kAlign = 256;   // output regions start on 256-byte boundarie
 
 uint64_t round_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-void size_erase(mtgp_server *s, uint64_t offset, uint64_t length)
-{
-    auto range = s->free_by_size.equal_range(length);
-    for (auto it = range.first; it != range.second; ++it)
-        if (it->second == offset) {
-            s->free_by_size.erase(it);
-            return;
-        }
-}
+void size_erase(mtgp_server *s, uint64_t offset, uint64_t length) { s->free_by_size.erase({length, offset}); }
 
-// Best fit: the smallest free range that holds `bytes` (ties: any), found
-// through the length index in O(log ranges).
+// Best fit: the smallest free range that holds `bytes` (ties: the lowest
+// offset), found through the length index in O(log ranges).
 bool take_range(mtgp_server *s, uint64_t bytes, uint64_t *offset)
 {
-    auto it = s->free_by_size.lower_bound(bytes);
+    auto it = s->free_by_size.lower_bound({bytes, 0});
     if (it == s->free_by_size.end())
         return false;
-    const uint64_t at = it->second, len = it->first;
+    const uint64_t len = it->first, at = it->second;
     s->free_by_size.erase(it);
     s->free_ranges.erase(at);
     *offset = at;
@@ -286,20 +291,20 @@ int launch_tick(mtgp_server *s)
         t.chunks.emplace_back(r, k);
     };
     // requests to split in this tick: polynomials ready, a state slot free,
-    // two or more segments' worth left
-    for (auto &kv : s->active)
-        for (Req *r : kv.second)
-            if (r->scheduled < r->n) {
-                if (!r->split && r->job && s->free_slots.size() > starts.size() && job_done(s, r->job)) {
-                    const uint64_t left = r->n - r->scheduled;
-                    const uint64_t S = std::min<uint64_t>(r->job->S, (left + r->job->J - 1) / r->job->J);
-                    if (left >= s->split_min && S >= 2)
-                        starts.push_back(SplitStart{r, (uint32_t)S, 0, 0});
-                    else
-                        r->job.reset();
-                }
-                break;   // a generator's oldest unfinished request only
+    // two or more segments' worth left (a generator's oldest request with
+    // outputs left to schedule only)
+    if (s->split_min > 0)
+        for (uint32_t g : s->ready) {
+            Req *r = s->gq[g].sched;
+            if (!r->split && r->job && s->free_slots.size() > starts.size() && job_done(s, r->job)) {
+                const uint64_t left = r->n - r->scheduled;
+                const uint64_t S = std::min<uint64_t>(r->job->S, (left + r->job->J - 1) / r->job->J);
+                if (left >= s->split_min && S >= 2)
+                    starts.push_back(SplitStart{r, (uint32_t)S, 0, 0});
+                else
+                    r->job.reset();
             }
+        }
     uint64_t ring_off = 0, ring_len = 0;
     if (!starts.empty()) {
         // staging block: polynomials, prefix items and jump items (uploaded),
@@ -383,36 +388,44 @@ int launch_tick(mtgp_server *s)
                 return MTGP_EDEVICE;
         }
     }
-    for (auto &kv : s->active) {
-        for (Req *r : kv.second) {
-            if (r->split && r->scheduled < r->n) {
-                uint32_t *pool = s->d_pool + (size_t)r->slot * s->split_max * s->nmax;
-                for (uint32_t k = 0; k < r->S; k++) {
-                    const uint64_t left = r->seg_len[k] - r->seg_sched[k];
-                    if (left == 0)
-                        continue;
-                    const uint64_t c = std::min(s->chunk, left);
-                    const bool last = r->seg_sched[k] + c == r->seg_len[k];
-                    // a segment's end state goes back to its buffer; at its end it is
-                    // dropped, except the last segment's, which is the generator's
-                    const uint16_t flags = !last ? mtgp_impl::kStateToSrc
-                                                 : (k + 1 == r->S ? (uint16_t)0 : mtgp_impl::kKeepState);
-                    add_item(r, r->base + (uint64_t)k * r->J + r->seg_sched[k], c,
-                             reinterpret_cast<uint64_t>(pool + (size_t)k * s->nmax), flags);
-                    r->seg_sched[k] += c;
-                    r->scheduled += c;
-                }
-                break;   // the generator's segments this tick
+    // one chunk per ready generator from its oldest request with outputs left
+    // (or one chunk of every segment of a split one); a request fully put in
+    // ticks passes the turn to the next one from the following tick on
+    s->ready_next.clear();
+    for (uint32_t g : s->ready) {
+        GenQ &q = s->gq[g];
+        Req *r = q.sched;
+        if (r->split) {
+            uint32_t *pool = s->d_pool + (size_t)r->slot * s->split_max * s->nmax;
+            for (uint32_t k = 0; k < r->S; k++) {
+                const uint64_t left = r->seg_len[k] - r->seg_sched[k];
+                if (left == 0)
+                    continue;
+                const uint64_t c = std::min(s->chunk, left);
+                const bool last = r->seg_sched[k] + c == r->seg_len[k];
+                // a segment's end state goes back to its buffer; at its end it is
+                // dropped, except the last segment's, which is the generator's
+                const uint16_t flags = !last ? mtgp_impl::kStateToSrc
+                                             : (k + 1 == r->S ? (uint16_t)0 : mtgp_impl::kKeepState);
+                add_item(r, r->base + (uint64_t)k * r->J + r->seg_sched[k], c,
+                         reinterpret_cast<uint64_t>(pool + (size_t)k * s->nmax), flags);
+                r->seg_sched[k] += c;
+                r->scheduled += c;
             }
-            if (r->scheduled < r->n) {
-                const uint64_t k = std::min(s->chunk, r->n - r->scheduled);
-                add_item(r, r->scheduled, k, 0, 0);
-                r->scheduled += k;
-                maybe_request_polys(s, r);
-                break;   // one chunk per generator per tick, from its oldest request
-            }
+        } else {
+            const uint64_t k = std::min(s->chunk, r->n - r->scheduled);
+            add_item(r, r->scheduled, k, 0, 0);
+            r->scheduled += k;
+            maybe_request_polys(s, r);
         }
+        if (r->scheduled == r->n)
+            q.sched = r->next;   // admitted later, so nothing of it is scheduled yet
+        if (q.sched)
+            s->ready_next.push_back(g);
+        else
+            q.ready = false;
     }
+    s->ready.swap(s->ready_next);
     if (t.chunks.empty())
         return MTGP_OK;
     if (s->spare_events.empty()) {
@@ -436,13 +449,54 @@ int launch_tick(mtgp_server *s)
     return MTGP_OK;
 }
 
-bool has_unscheduled(const mtgp_server *s)
+bool has_unscheduled(const mtgp_server *s) { return !s->ready.empty(); }
+
+Req *new_req(mtgp_server *s, const mtgp_server_request &q)
 {
-    for (const auto &kv : s->active)
-        for (const Req *r : kv.second)
-            if (r->scheduled < r->n)
-                return true;
-    return false;
+    Req *r;
+    if (!s->req_pool.empty()) {
+        r = s->req_pool.back();
+        s->req_pool.pop_back();
+        *r = Req{q.rid, q.gen, q.kind, q.n};
+    } else {
+        r = new (std::nothrow) Req{q.rid, q.gen, q.kind, q.n};
+    }
+    return r;
+}
+
+// Put r at the end of its generator's queue (admission).
+void gq_push(mtgp_server *s, Req *r)
+{
+    GenQ &q = s->gq[r->gen];
+    r->next = nullptr;
+    if (q.tail)
+        q.tail->next = r;
+    else
+        q.head = r;
+    q.tail = r;
+    if (!q.sched)
+        q.sched = r;
+    if (!q.ready) {
+        q.ready = true;
+        s->ready.push_back(r->gen);
+    }
+    s->active++;
+}
+
+// Take finished r out of its generator's queue (it is the head whenever
+// requests finish in arrival order, which one chunk per generator per tick
+// keeps; the walk covers any other case).
+void gq_remove(mtgp_server *s, Req *r)
+{
+    GenQ &q = s->gq[r->gen];
+    Req *prev = nullptr;
+    for (Req *x = q.head; x && x != r; x = x->next)
+        prev = x;
+    (prev ? prev->next : q.head) = r->next;
+    if (q.tail == r)
+        q.tail = prev;
+    r->next = nullptr;
+    s->active--;
 }
 
 }  // namespace
@@ -468,6 +522,7 @@ mtgp_server_t *mtgp_server_create(mtgp_batch_t *b, void *arena, uint64_t arena_b
     s->stream = static_cast<hipStream_t>(stream);
     s->free_ranges.emplace(0, s->arena_bytes);
     s->free_by_size.emplace(s->arena_bytes, 0);
+    s->gq.resize(mtgp_batch_size(b));
     return s;
 }
 
@@ -483,7 +538,7 @@ int mtgp_server_submit(mtgp_server_t *s, const mtgp_server_request *reqs, uint32
             return MTGP_EINVAL;
     }
     for (uint32_t i = 0; i < count; i++) {
-        Req *r = new (std::nothrow) Req{reqs[i].rid, reqs[i].gen, reqs[i].kind, reqs[i].n};
+        Req *r = new_req(s, reqs[i]);
         if (!r)
             return MTGP_ENOMEM;
         s->waiting.push_back(r);
@@ -511,14 +566,7 @@ int mtgp_server_poll(mtgp_server_t *s, mtgp_completion *done, uint32_t max_done,
                     s->free_slots.push_back(r->slot);
                     r->split = false;
                 }
-                auto &q2 = s->active[r->gen];
-                for (auto it = q2.begin(); it != q2.end(); ++it)
-                    if (*it == r) {
-                        q2.erase(it);
-                        break;
-                    }
-                if (q2.empty())
-                    s->active.erase(r->gen);
+                gq_remove(s, r);
                 s->completed[r->rid] = r;
                 s->unreported.push_back(mtgp_completion{r->rid, r->offset, r->n});
             }
@@ -539,7 +587,7 @@ int mtgp_server_poll(mtgp_server_t *s, mtgp_completion *done, uint32_t max_done,
             break;
         r->offset = off;
         s->waiting.pop_front();
-        s->active[r->gen].push_back(r);
+        gq_push(s, r);
         maybe_request_polys(s, r);
     }
     while (s->inflight.size() < s->depth && has_unscheduled(s)) {
@@ -566,7 +614,7 @@ int mtgp_server_release(mtgp_server_t *s, const uint64_t *rids, uint32_t count)
         Req *r = it->second;
         give_range(s, r->offset, round_up(4u * r->n));
         s->completed.erase(it);
-        delete r;
+        s->req_pool.push_back(r);
     }
     return rc;
 }
@@ -575,13 +623,10 @@ int mtgp_server_pending(const mtgp_server_t *s, uint64_t *waiting, uint64_t *act
 {
     if (!s)
         return MTGP_EINVAL;
-    uint64_t a = 0;
-    for (const auto &kv : s->active)
-        a += kv.second.size();
     if (waiting)
         *waiting = s->waiting.size();
     if (active)
-        *active = a;
+        *active = s->active;
     if (inflight)
         *inflight = (uint32_t)s->inflight.size();
     return MTGP_OK;
@@ -648,11 +693,16 @@ void mtgp_server_destroy(mtgp_server_t *s)
         (void)hipEventDestroy(e);
     for (Req *r : s->waiting)
         delete r;
-    for (auto &kv : s->active)
-        for (Req *r : kv.second)
+    for (GenQ &q : s->gq)
+        for (Req *r = q.head; r;) {
+            Req *nx = r->next;
             delete r;
+            r = nx;
+        }
     for (auto &kv : s->completed)
         delete kv.second;
+    for (Req *r : s->req_pool)
+        delete r;
     (void)hipFree(s->d_pool);
     (void)hipFree(s->d_ring);
     if (s->h_ring)
