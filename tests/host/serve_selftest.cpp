@@ -1,0 +1,174 @@
+// CPU self-test of the request loop (csrc/mtgp_serve.cpp) over a stand-in
+// device: the batch launch records its work items instead of running them,
+// and events complete after a few polls (tests/host/mockhip). For random
+// request streams it checks that every request completes exactly once with
+// its size, that no generator gets two chunks in one tick, and that each
+// generator's chunks, in launch order, cover its requests in arrival order,
+// each one contiguously from its first output to its last. Built and run
+// under AddressSanitizer and UndefinedBehaviorSanitizer by
+// tests/test_host_sanitizers.py.
+#include "mtgp.h"
+#include "mtgp_host.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+struct mtgp_batch {
+    uint32_t count;
+};
+
+static std::vector<std::vector<mtgp_impl::WorkItem>> g_launches;
+
+extern "C" uint32_t mtgp_batch_size(const mtgp_batch_t *b) { return b->count; }
+
+namespace mtgp_impl {
+int launch_work_items(mtgp_batch_t *, std::vector<WorkItem> &items, hipStream_t)
+{
+    g_launches.push_back(items);
+    return MTGP_OK;
+}
+// no generator is prepared for jump-ahead: these are never reached
+bool split_ready(const mtgp_batch_t *, uint32_t) { return false; }
+const f2::Poly &split_psi(const mtgp_batch_t *, uint32_t)
+{
+    static f2::Poly p;
+    return p;
+}
+uint32_t gen_words(const mtgp_batch_t *, uint32_t) { return 351; }
+uint32_t max_gen_words(const mtgp_batch_t *) { return 351; }
+uint32_t poly_words(uint32_t, uint32_t) { return 1; }
+void poly_layout(const f2::Poly &, uint32_t, uint64_t *) {}
+std::vector<f2::Poly> segment_polys(const f2::Poly &, uint64_t, uint32_t) { return {}; }
+LaunchShape prefix_shape(const mtgp_batch_t *, const std::vector<uint32_t> &) { return LaunchShape{}; }
+uint16_t prefix_spl(const mtgp_batch_t *, uint32_t, const LaunchShape &) { return 1; }
+hipError_t launch_prefix(mtgp_batch_t *, const WorkItem *, uint32_t, const LaunchShape &, hipStream_t)
+{
+    return hipSuccess;
+}
+hipError_t launch_jumps(const JumpItem *, const JumpItem *, uint32_t, hipStream_t) { return hipSuccess; }
+}  // namespace mtgp_impl
+
+static uint64_t g_rng = 88172645463325252ull;
+static uint64_t rnd()
+{
+    g_rng ^= g_rng << 13;
+    g_rng ^= g_rng >> 7;
+    g_rng ^= g_rng << 17;
+    return g_rng;
+}
+
+static int failures = 0;
+#define CHECK(cond, ...)                          \
+    do {                                          \
+        if (!(cond)) {                            \
+            if (failures++ < 10) {                \
+                std::printf("FAIL: " __VA_ARGS__); \
+                std::printf("\n");                \
+            }                                     \
+        }                                         \
+    } while (0)
+
+// One request stream: G generators, nreq requests (a fifth of them up to
+// `big` outputs), submitted a few at a time between polls.
+static void run_stream(uint32_t G, uint32_t nreq, uint64_t big, uint64_t chunk, uint32_t depth, uint64_t arena_bytes)
+{
+    mtgp_batch b{G};
+    void *arena = std::aligned_alloc(256, arena_bytes);
+    mtgp_server_t *s = mtgp_server_create(&b, arena, arena_bytes, chunk, depth, nullptr);
+    CHECK(s != nullptr, "create");
+    if (!s)
+        return;
+    CHECK(mtgp_server_set_split(s, 1 << 16, 8, 2, 4) == MTGP_EINVAL, "split ticks are refused");
+    std::vector<mtgp_server_request> reqs(nreq);
+    for (uint32_t i = 0; i < nreq; i++) {
+        reqs[i].rid = 1000 + i;
+        reqs[i].gen = (uint32_t)(rnd() % G);
+        reqs[i].kind = (uint32_t)(rnd() % 4);
+        reqs[i].n = 1 + rnd() % (i % 5 == 0 ? big : 20000);
+        if (reqs[i].kind == 3)
+            reqs[i].n += reqs[i].n & 1;
+    }
+    g_launches.clear();
+    std::vector<mtgp_completion> done(4096);
+    std::vector<int> seen(nreq, 0);
+    size_t next = 0, finished = 0;
+    long polls = 0;
+    while (finished < nreq && polls < 5000000) {
+        if (next < nreq) {
+            const size_t k = std::min<size_t>(1 + rnd() % 16, nreq - next);
+            CHECK(mtgp_server_submit(s, &reqs[next], (uint32_t)k) == MTGP_OK, "submit");
+            next += k;
+        }
+        uint32_t nd = 0;
+        CHECK(mtgp_server_poll(s, done.data(), (uint32_t)done.size(), &nd) == MTGP_OK, "poll");
+        std::vector<uint64_t> rel;
+        for (uint32_t i = 0; i < nd; i++) {
+            const uint64_t k = done[i].rid - 1000;
+            CHECK(k < nreq && done[i].n == reqs[k].n, "completion %llu", (unsigned long long)done[i].rid);
+            if (k < nreq)
+                seen[k]++;
+            rel.push_back(done[i].rid);
+        }
+        if (!rel.empty())
+            CHECK(mtgp_server_release(s, rel.data(), (uint32_t)rel.size()) == MTGP_OK, "release");
+        finished += nd;
+        polls++;
+    }
+    for (uint32_t i = 0; i < nreq; i++)
+        CHECK(seen[i] == 1, "request %u completed %d times", i, seen[i]);
+    // per generator, the chunks in launch order against its requests in arrival order
+    std::vector<std::vector<uint32_t>> order(G);
+    for (uint32_t i = 0; i < nreq; i++)
+        order[reqs[i].gen].push_back(i);
+    std::vector<size_t> cur(G, 0);
+    std::vector<uint64_t> left(G, 0), next_out(G, 0);
+    for (uint32_t g = 0; g < G; g++)
+        if (!order[g].empty())
+            left[g] = reqs[order[g][0]].n;
+    for (const auto &L : g_launches) {
+        std::vector<int> per(G, 0);
+        for (const auto &it : L) {
+            const uint32_t g = it.gen;
+            CHECK(g < G && per[g]++ == 0, "generator %u twice in a tick", g);
+            if (g >= G || cur[g] >= order[g].size()) {
+                CHECK(false, "chunk beyond the requests of generator %u", g);
+                continue;
+            }
+            const mtgp_server_request &q = reqs[order[g][cur[g]]];
+            CHECK((it.kind & 0xff) == q.kind && it.n > 0 && it.n <= chunk && it.n <= left[g] && it.src == 0,
+                  "chunk of generator %u", g);
+            CHECK(left[g] == q.n || it.out == next_out[g], "chunks of a request not contiguous (generator %u)", g);
+            const uint64_t off = it.out - reinterpret_cast<uint64_t>(arena);
+            CHECK(off % 4 == 0 && off + 4 * it.n <= arena_bytes, "chunk outside the arena");
+            next_out[g] = it.out + 4 * it.n;
+            left[g] -= std::min(left[g], it.n);
+            if (left[g] == 0 && ++cur[g] < order[g].size())
+                left[g] = reqs[order[g][cur[g]]].n;
+        }
+    }
+    for (uint32_t g = 0; g < G; g++)
+        CHECK(cur[g] == order[g].size(), "generator %u: %zu of %zu requests covered", g, cur[g], order[g].size());
+    uint64_t waiting = 1, active = 1;
+    uint32_t inflight = 1;
+    mtgp_server_pending(s, &waiting, &active, &inflight);
+    CHECK(waiting == 0 && active == 0 && inflight == 0, "pending after the stream");
+    std::printf("stream G=%u requests=%u chunk=%llu depth=%u: %ld polls, %zu ticks\n", G, nreq,
+                (unsigned long long)chunk, depth, polls, g_launches.size());
+    mtgp_server_destroy(s);
+    std::free(arena);
+}
+
+int main()
+{
+    run_stream(64, 3000, 300000, 1 << 14, 2, 64ull << 20);
+    run_stream(8, 2000, 300000, 1 << 12, 3, 64ull << 20);
+    run_stream(1000, 20000, 300000, 1 << 16, 1, 64ull << 20);
+    // an arena smaller than the load: admission waits for releases
+    run_stream(32, 4000, 100000, 1 << 13, 2, 2ull << 20);
+    if (failures)
+        std::printf("%d failures\n", failures);
+    else
+        std::printf("serve selftest ok\n");
+    return failures ? 1 : 0;
+}

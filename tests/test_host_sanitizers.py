@@ -1,7 +1,8 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
 
 The library's device-free C++ sources (F2 polynomial arithmetic, the
-parameter search, the dimension of equidistribution) and the C oracle are
+parameter search, the dimension of equidistribution), the request loop over a
+stand-in device, and the C oracle are
 built with g++/gcc, -fsanitize=address,undefined and no recovery, and run
 their self-tests (tests/host/*): any leak, out-of-bounds access, overflow of
 a signed type or other undefined behaviour ends the run with an error.
@@ -34,6 +35,14 @@ def test_library_host_code_under_sanitizers(tmp_path):
     srcs = [os.path.join(ROOT, "tests", "host", "host_selftest.cpp")] + \
         [os.path.join(CSRC, f) for f in ("mtgp_f2.cpp", "mtgp_dc.cpp", "mtgp_equidist.cpp")]
     build_and_run(tmp_path, "g++", srcs, ["-std=c++17", "-I", os.path.join(ROOT, "include")], "host selftest ok")
+
+
+def test_request_loop_under_sanitizers(tmp_path):
+    """The request loop's host logic over a stand-in device (tests/host/mockhip)."""
+    srcs = [os.path.join(ROOT, "tests", "host", "serve_selftest.cpp"),
+            os.path.join(CSRC, "mtgp_serve.cpp"), os.path.join(CSRC, "mtgp_f2.cpp")]
+    build_and_run(tmp_path, "g++", srcs, ["-std=c++17", "-I", os.path.join(ROOT, "tests", "host", "mockhip"),
+                                          "-I", os.path.join(ROOT, "include"), "-I", CSRC], "serve selftest ok")
 
 
 def test_oracle_under_sanitizers(tmp_path):
