@@ -489,9 +489,11 @@ void gq_push(mtgp_server *s, Req *r)
 void gq_remove(mtgp_server *s, Req *r)
 {
     GenQ &q = s->gq[r->gen];
-    Req *prev = nullptr;
-    for (Req *x = q.head; x && x != r; x = x->next)
+    Req *prev = nullptr, *x = q.head;
+    for (; x && x != r; x = x->next)
         prev = x;
+    if (!x)
+        return;   // not queued (cannot happen: admitted requests stay queued until they finish)
     (prev ? prev->next : q.head) = r->next;
     if (q.tail == r)
         q.tail = prev;
