@@ -299,6 +299,14 @@ struct mtgp_plan {
     LaunchShape pshape;                        // launch shape of the raw prefix
     JumpItem *d_jumps = nullptr;               // jump items (in d_items' allocation)
     std::vector<JumpItem> jumps;               // host copy, grouped by lane width
+    // the jump launches (one per lane width and word-group count) as two
+    // branches of the captured graph: the run with the most work (its jumps'
+    // D N summed) on the capture stream, the other runs one after another on
+    // a side stream; run k = items [runs[k], runs[k + 1])
+    std::vector<uint32_t> runs;
+    uint32_t heavy = 0;                        // the run on the capture stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -532,6 +540,12 @@ void plan_free(mtgp_plan *p)
     }
     if (p->capture)
         (void)hipStreamDestroy(p->capture);
+    if (p->side)
+        (void)hipStreamDestroy(p->side);
+    if (p->ev_fork)
+        (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join)
+        (void)hipEventDestroy(p->ev_join);
     (void)hipFree(p->d_items);
     (void)hipFree(p->d_counters);
     (void)hipFree(p->d_jump_mem);
@@ -550,8 +564,23 @@ bool capture_phases(mtgp_plan *p, int mask, hipGraph_t &graph, hipGraphExec_t &e
     hipError_t le = hipSuccess;
     if ((mask & 1) && p->nprefix > 0) {
         le = launch_generate(b->d_recs, b->d_states, p->d_prefix, p->nprefix, nullptr, none, p->pshape, p->capture);
-        if (le == hipSuccess)
+        if (le == hipSuccess && !p->side) {
             le = launch_jumps(p->d_jumps, p->jumps.data(), (uint32_t)p->jumps.size(), p->capture);
+        } else if (le == hipSuccess) {
+            // fork after the raw prefix: the heaviest run here, the others on
+            // the side stream; joined whatever happened, so the capture can end
+            le = hipEventRecord(p->ev_fork, p->capture);
+            if (le == hipSuccess)
+                le = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+            for (size_t k = 0; k + 1 < p->runs.size() && le == hipSuccess; k++) {
+                const uint32_t a = p->runs[k], n = p->runs[k + 1] - a;
+                le = launch_jumps(p->d_jumps + a, p->jumps.data() + a, n, k == p->heavy ? p->capture : p->side);
+            }
+            const hipError_t je = hipEventRecord(p->ev_join, p->side);
+            const hipError_t we = je == hipSuccess ? hipStreamWaitEvent(p->capture, p->ev_join, 0) : je;
+            if (le == hipSuccess)
+                le = we;
+        }
     }
     if ((mask & 2) && le == hipSuccess)
         le = launch_generate(b->d_recs, b->d_states, p->d_items, (uint32_t)p->items.size(), p->d_counters, none,
@@ -1704,6 +1733,32 @@ mtgp_plan_t *mtgp_batch_plan_create(mtgp_batch_t *b, const mtgp_request *reqs, u
         plan_free(p);
         fail(MTGP_EDEVICE);
         return nullptr;
+    }
+    // runs of jump items with one launch shape (the items are grouped so)
+    for (uint32_t i = 0; i < (uint32_t)p->jumps.size(); i++) {
+        const JumpShape a = jump_shape(p->jumps[i].N);
+        if (i == 0 || a.R != jump_shape(p->jumps[i - 1].N).R || a.G != jump_shape(p->jumps[i - 1].N).G)
+            p->runs.push_back(i);
+    }
+    p->runs.push_back((uint32_t)p->jumps.size());
+    if (p->runs.size() > 2) {
+        uint64_t most = 0;
+        for (size_t k = 0; k + 1 < p->runs.size(); k++) {
+            uint64_t work = 0;
+            for (uint32_t i = p->runs[k]; i < p->runs[k + 1]; i++)
+                work += (uint64_t)p->jumps[i].D * p->jumps[i].N;
+            if (work > most) {
+                most = work;
+                p->heavy = (uint32_t)k;
+            }
+        }
+        if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
+            plan_free(p);
+            fail(MTGP_EDEVICE);
+            return nullptr;
+        }
     }
     bool ok = true;
     for (int k = 0; k < 3 && ok; k++)
