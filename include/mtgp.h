@@ -300,7 +300,8 @@ int mtgp_plan_items(const mtgp_plan_t *p, uint64_t *outs, uint64_t *ns, uint32_t
  * at the split limit that cuts the same segment lengths as the best one so
  * far (split limits count rounds of the shape in use) and at half of it,
  * then the best of these with the other recursion-table
- * form (MTGP_MODE_REC_BASIS) -- and keeps the fastest (a later candidate must be at least
+ * form (MTGP_MODE_REC_BASIS), then the best so far with its split limit
+ * times 1.3 and divided by 1.3 -- and keeps the fastest (a later candidate must be at least
  * 2 % faster than the one it replaces) as the batch's launch shape
  * (mtgp_batch_set_launch) and split limit (mtgp_batch_set_split). Outputs are
  * identical under every configuration; the generators' states and counters

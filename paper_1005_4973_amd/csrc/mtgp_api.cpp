@@ -15,6 +15,7 @@ static_assert(mtgp_impl::kStaticScratchBytes == MTGP_STATIC_SCRATCH_BYTES, "allo
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstring>
 #include <functional>
 #include <new>
@@ -2022,6 +2023,20 @@ int mtgp_batch_autotune(mtgp_batch_t *b, const mtgp_request *reqs, uint32_t nreq
         c.shape.rec_basis = 1 - c.shape.rec_basis;
         trial(c);
         tried.push_back(c);
+    }
+    // a local step around the best split limit: the candidates above are a
+    // factor of two apart (or fixed fractions of the fair share), and the
+    // best limit often lies between them
+    if (device_ok && best_of().split > 0) {
+        const Cand base = best_of();
+        for (const double f : {1.3, 1.0 / 1.3}) {
+            Cand c = base;
+            c.split = (uint32_t)std::max(128.0, std::round((double)base.split * f));
+            if (!device_ok || c.split == base.split)
+                continue;
+            trial(c);
+            tried.push_back(c);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

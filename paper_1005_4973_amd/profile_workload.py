@@ -5,9 +5,11 @@ Runs, in order:
      WRITE_SIZE readings calibrate the counters (1 GiB read, 1 GiB written);
   2. one workload as bench.py times it, in a given configuration (split
      limit and launch shape) or autotuned on its requests (the chosen
-     configuration is printed); the plan is replayed three times as its two
-     phases (prepare: raw prefix and jump kernels; generate: the persistent
-     generation kernel). Counters of the last replay are the ones to read.
+     configuration is printed); the plan is replayed twelve times back to
+     back, each replay as its two phases (prepare: raw prefix and jump
+     kernels; generate: the persistent generation kernel), as the benchmark
+     queues its replays. The last replays are the warm ones to read (the
+     first run cold); counters of the last replay are the ones to read.
      Workloads:
        batched_uneven   4096 generators (11213:23209:44497 = 2:1:1), lengths
                         log-uniform in [2^10, 2^24], mixed kinds (the headline)
@@ -29,6 +31,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 COPY_BYTES = 1 << 30
+
+
+REPLAYS = 12
 
 
 def main():
@@ -79,10 +84,10 @@ def main():
     print("split_rounds: {}".format(args.split if args.split is not None else "autotuned (see above)"), flush=True)
     print("launch: " + " ".join(f"{k}={d[k]}" for k in ("mode", "threads", "spl", "lds_words", "grid")), flush=True)
     print(f"work items: {d['items']}, jumps: {d['jumps']}", flush=True)
-    for _ in range(3):
+    for _ in range(REPLAYS):
         plan.launch_phase(mtgp.PHASE_PREPARE)
         plan.launch_phase(mtgp.PHASE_GENERATE)
-        torch.cuda.synchronize()
+    torch.cuda.synchronize()
     if args.probe:
         # the store-only probe over the same work items in queue order, on as
         # many wavefronts as the launch runs items at once (one warm-up and
