@@ -1,10 +1,10 @@
 // Continuous-batching request loop over a batch's resident generators.
 //
 // Requests (generator, kind, n) are queued by the caller and admitted in
-// arrival order while their outputs fit the output arena (best fit: the
-// smallest free range that holds the request, found through an index of the
-// free ranges by length; a request that does not fit waits, and so do the
-// ones behind it). Every
+// arrival order while their outputs fit the output arena (a free range from
+// a two-level segregated-fit index, mtgp_arena.h: constant time, and it fails
+// only when no free range can hold the request; a request that does not fit
+// waits, and so do the ones behind it). Every
 // scheduling step retires ticks whose completion event has fired, admits
 // what fits, and launches ticks while fewer than `depth` are in flight. A
 // tick advances every generator that has admitted work by up to `chunk`
@@ -28,6 +28,7 @@
 // in order; nothing in the loop allocates device memory or waits for the
 // device.
 #include "../../include/mtgp.h"
+#include "mtgp_arena.h"
 #include "mtgp_host.h"
 
 #include <hip/hip_runtime.h>
@@ -36,11 +37,9 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
-#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -72,6 +71,7 @@ struct Req {
     uint64_t n;
     Req *next = nullptr;     // the generator's next admitted request
     uint64_t offset = 0;     // byte offset of its outputs in the arena
+    uint32_t blk = 0;        // its block in the arena index
     uint64_t scheduled = 0;  // outputs put in ticks
     uint64_t finished = 0;   // outputs whose tick completed
     // jump-ahead
@@ -107,8 +107,7 @@ struct mtgp_server {
     uint64_t chunk = 0;
     uint32_t depth = 0;
     hipStream_t stream = nullptr;
-    std::map<uint64_t, uint64_t> free_ranges;              // offset -> length, disjoint and coalesced
-    std::set<std::pair<uint64_t, uint64_t>> free_by_size;  // (length, offset) of the same ranges
+    std::unique_ptr<mtgp_impl::ArenaIndex> index;         // free ranges of the arena, in kAlign units
     std::deque<Req *> waiting;                             // submitted, not admitted
     std::vector<GenQ> gq;                                  // per generator: admitted, unfinished
     std::vector<uint32_t> ready, ready_next;               // generators with outputs to put in ticks
@@ -138,48 +137,6 @@ namespace {
 constexpr uint64_t kAlign = 256;   // output regions start on 256-byte boundaries
 
 uint64_t round_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-void size_erase(mtgp_server *s, uint64_t offset, uint64_t length) { s->free_by_size.erase({length, offset}); }
-
-// Best fit: the smallest free range that holds `bytes` (ties: the lowest
-// offset), found through the length index in O(log ranges).
-bool take_range(mtgp_server *s, uint64_t bytes, uint64_t *offset)
-{
-    auto it = s->free_by_size.lower_bound({bytes, 0});
-    if (it == s->free_by_size.end())
-        return false;
-    const uint64_t len = it->first, at = it->second;
-    s->free_by_size.erase(it);
-    s->free_ranges.erase(at);
-    *offset = at;
-    if (len > bytes) {
-        s->free_ranges.emplace(at + bytes, len - bytes);
-        s->free_by_size.emplace(len - bytes, at + bytes);
-    }
-    return true;
-}
-
-void give_range(mtgp_server *s, uint64_t offset, uint64_t bytes)
-{
-    auto it = s->free_ranges.emplace(offset, bytes).first;
-    // merge with the following and the preceding range
-    auto next = std::next(it);
-    if (next != s->free_ranges.end() && it->first + it->second == next->first) {
-        size_erase(s, next->first, next->second);
-        it->second += next->second;
-        s->free_ranges.erase(next);
-    }
-    if (it != s->free_ranges.begin()) {
-        auto prev = std::prev(it);
-        if (prev->first + prev->second == it->first) {
-            size_erase(s, prev->first, prev->second);
-            prev->second += it->second;
-            s->free_ranges.erase(it);
-            it = prev;
-        }
-    }
-    s->free_by_size.emplace(it->second, it->first);
-}
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
@@ -522,8 +479,11 @@ mtgp_server_t *mtgp_server_create(mtgp_batch_t *b, void *arena, uint64_t arena_b
         s->chunk = 2;
     s->depth = depth;
     s->stream = static_cast<hipStream_t>(stream);
-    s->free_ranges.emplace(0, s->arena_bytes);
-    s->free_by_size.emplace(s->arena_bytes, 0);
+    s->index.reset(new (std::nothrow) mtgp_impl::ArenaIndex(s->arena_bytes / kAlign));
+    if (!s->index) {
+        delete s;
+        return nullptr;
+    }
     s->gq.resize(mtgp_batch_size(b));
     return s;
 }
@@ -584,10 +544,11 @@ int mtgp_server_poll(mtgp_server_t *s, mtgp_completion *done, uint32_t max_done,
     // admit in arrival order while the head fits
     while (!s->waiting.empty()) {
         Req *r = s->waiting.front();
-        uint64_t off;
-        if (!take_range(s, round_up(4u * r->n), &off))
+        const uint32_t blk = s->index->take(round_up(4u * r->n) / kAlign);
+        if (blk == mtgp_impl::ArenaIndex::kNil)
             break;
-        r->offset = off;
+        r->blk = blk;
+        r->offset = s->index->offset(blk) * kAlign;
         s->waiting.pop_front();
         gq_push(s, r);
         maybe_request_polys(s, r);
@@ -614,7 +575,7 @@ int mtgp_server_release(mtgp_server_t *s, const uint64_t *rids, uint32_t count)
             continue;
         }
         Req *r = it->second;
-        give_range(s, r->offset, round_up(4u * r->n));
+        s->index->give(r->blk);
         s->completed.erase(it);
         s->req_pool.push_back(r);
     }

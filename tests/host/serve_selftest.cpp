@@ -8,8 +8,10 @@
 // under AddressSanitizer and UndefinedBehaviorSanitizer by
 // tests/test_host_sanitizers.py.
 #include "mtgp.h"
+#include "mtgp_arena.h"
 #include "mtgp_host.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -159,8 +161,75 @@ static void run_stream(uint32_t G, uint32_t nreq, uint64_t big, uint64_t chunk, 
     std::free(arena);
 }
 
+// The arena index against a plain model: after every take and give, the free
+// blocks are exactly the units not taken (disjoint, merged with free
+// neighbours), a take fails only when no free block holds the request, and
+// taken blocks never overlap.
+static void test_arena_index()
+{
+    for (uint64_t units : {1ull, 15ull, 16ull, 17ull, 1000ull, 1ull << 20, (1ull << 25) + 3}) {
+        mtgp_impl::ArenaIndex ix(units);
+        std::vector<std::pair<uint32_t, uint64_t>> live;   // (id, length)
+        std::vector<uint8_t> used((size_t)std::min<uint64_t>(units, 1 << 20) , 0);
+        const bool model = units <= (1u << 20);
+        for (int step = 0; step < 4000; step++) {
+            if (live.empty() || rnd() % 3) {
+                const uint64_t want = 1 + (rnd() % 4 == 0 ? rnd() % units : rnd() % std::min<uint64_t>(units, 64));
+                uint64_t largest = 0;
+                for (auto &fb : ix.free_blocks())
+                    largest = std::max(largest, fb.second);
+                const uint32_t id = ix.take(want);
+                CHECK((id == mtgp_impl::ArenaIndex::kNil) == (largest < want), "take %llu of %llu: largest free %llu",
+                      (unsigned long long)want, (unsigned long long)units, (unsigned long long)largest);
+                if (id == mtgp_impl::ArenaIndex::kNil)
+                    continue;
+                CHECK(ix.length(id) == want && ix.offset(id) + want <= units, "taken block");
+                if (model)
+                    for (uint64_t u = ix.offset(id); u < ix.offset(id) + want; u++) {
+                        CHECK(!used[u], "overlap at unit %llu", (unsigned long long)u);
+                        used[u] = 1;
+                    }
+                live.emplace_back(id, want);
+            } else {
+                const size_t k = rnd() % live.size();
+                const uint32_t id = live[k].first;
+                if (model)
+                    for (uint64_t u = ix.offset(id); u < ix.offset(id) + live[k].second; u++)
+                        used[u] = 0;
+                ix.give(id);
+                live[k] = live.back();
+                live.pop_back();
+            }
+            if (model && step % 97 == 0) {
+                // free blocks = maximal runs of unused units
+                std::vector<std::pair<uint64_t, uint64_t>> runs;
+                for (uint64_t u = 0; u < units;) {
+                    if (used[u]) {
+                        u++;
+                        continue;
+                    }
+                    uint64_t e = u;
+                    while (e < units && !used[e])
+                        e++;
+                    runs.emplace_back(u, e - u);
+                    u = e;
+                }
+                auto fb = ix.free_blocks();
+                std::sort(fb.begin(), fb.end());
+                CHECK(fb == runs, "free blocks differ from the model (%zu against %zu runs)", fb.size(), runs.size());
+            }
+        }
+        for (auto &l : live)
+            ix.give(l.first);
+        const auto fb = ix.free_blocks();
+        CHECK(fb.size() == 1 && fb[0].first == 0 && fb[0].second == units, "everything given back: one block");
+    }
+    std::printf("arena index checked\n");
+}
+
 int main()
 {
+    test_arena_index();
     run_stream(64, 3000, 300000, 1 << 14, 2, 64ull << 20);
     run_stream(8, 2000, 300000, 1 << 12, 3, 64ull << 20);
     run_stream(1000, 20000, 300000, 1 << 16, 1, 64ull << 20);
