@@ -167,14 +167,24 @@ uint32_t max_window_words(const LaunchShape &s, size_t max_lds)
 
 // Whether the chunked form with read-ahead `depth` can run a generator
 // (N - M >= 64 (depth + 2), and a ring it is built for).
-bool chunk_ok(const GenRecord &r, uint32_t depth)
+// A generator's state words and M, kept beside the batch's records in a
+// compact array: the per-item passes of every launch (shape, checks, order)
+// read only these, and 8 bytes a generator stay in cache where the 256-byte
+// records of tens of thousands of generators do not.
+struct GenShape {
+    uint32_t N, M;
+};
+
+template <class R>
+bool chunk_ok(const R &r, uint32_t depth)
 {
     return r.N - r.M >= chunk_min_gap(depth) && chunk_ring_words(r.N) <= kChunkMaxRing;
 }
 
 // Window a generator needs under a shape: 2N + lanes * item_spl words; the
 // chunked form's ring length (no length serves a generator it cannot run).
-uint32_t window_need(const GenRecord &r, const LaunchShape &s)
+template <class R>
+uint32_t window_need(const R &r, const LaunchShape &s)
 {
     if (s.mode == kModeChunk)
         return chunk_ok(r, (uint32_t)s.spl) ? chunk_ring_words(r.N) : UINT32_MAX;
@@ -251,6 +261,7 @@ struct mtgp {
 struct mtgp_batch {
     uint32_t count = 0;
     std::vector<GenRecord> recs;
+    std::vector<GenShape> gs;       // N and M of each record, compact
     std::vector<uint64_t> consumed;
     GenRecord *d_recs = nullptr;
     uint32_t *d_states = nullptr;
@@ -356,13 +367,13 @@ LaunchShape chunk_shape(const mtgp_batch *b, Items items, int threads = 256, int
     if (depth == 0) {
         depth = 2;
         for (const WorkItem &it : items)
-            if (!chunk_ok(b->recs[it.gen], 2))
+            if (!chunk_ok(b->gs[it.gen], 2))
                 depth = 1;
     }
     s.spl = depth;
     uint32_t L = 512;
     for (const WorkItem &it : items)
-        L = std::max(L, chunk_ring_words(b->recs[it.gen].N));
+        L = std::max(L, chunk_ring_words(b->gs[it.gen].N));
     s.lds_words = (int)L;
     const uint32_t units = (uint32_t)threads / 64u;
     const uint32_t by_lds = (uint32_t)(kLdsPerCu / (chunk_unit_words(L) * 4u)) / units;
@@ -375,7 +386,7 @@ LaunchShape chunk_shape(const mtgp_batch *b, Items items, int threads = 256, int
 bool all_chunk_ok(const mtgp_batch *b, Items items, uint32_t depth = 1)
 {
     for (const WorkItem &it : items)
-        if (!chunk_ok(b->recs[it.gen], depth))
+        if (!chunk_ok(b->gs[it.gen], depth))
             return false;
     return !items.empty();
 }
@@ -390,7 +401,7 @@ LaunchShape batch_default_shape(const mtgp_batch *b, Items items, int threads = 
     s.grid = 1;
     uint32_t need = 0;
     for (const WorkItem &it : items)
-        need = std::max(need, window_need(b->recs[it.gen], s));
+        need = std::max(need, window_need(b->gs[it.gen], s));
     s.lds_words = 1;
     const uint32_t cap = max_window_words(s, b->max_lds);
     const uint32_t by_waves = std::max(1u, kWavesPerCu / (uint32_t)(s.threads / 64));
@@ -424,7 +435,7 @@ int resolve_shape(const mtgp_batch *b, Items items, LaunchShape &out)
         if (s.lds_words == 0) {
             uint32_t need = 0;
             for (const WorkItem &it : items)
-                need = std::max(need, window_need(b->recs[it.gen], s));
+                need = std::max(need, window_need(b->gs[it.gen], s));
             s.lds_words = (int)need;
         }
         if (s.grid == 0) {
@@ -440,7 +451,7 @@ int resolve_shape(const mtgp_batch *b, Items items, LaunchShape &out)
     if (!shape_valid(s, b->max_lds))
         return MTGP_EINVAL;
     for (const WorkItem &it : items)
-        if ((uint32_t)s.lds_words < window_need(b->recs[it.gen], s))
+        if ((uint32_t)s.lds_words < window_need(b->gs[it.gen], s))
             return MTGP_EINVAL;
     out = s;
     return MTGP_OK;
@@ -496,7 +507,7 @@ void finish_items(const mtgp_batch *b, std::vector<WorkItem> &items, const Launc
     std::vector<std::pair<uint64_t, uint32_t>> key(items.size());
     for (size_t i = 0; i < items.size(); i++) {
         WorkItem &it = items[i];
-        const GenRecord &r = b->recs[it.gen];
+        const GenShape &r = b->gs[it.gen];
         it.spl = item_spl(r.N, r.M, s);
         const uint64_t w = round_width(r.N, r.M, s);
         key[i] = {(it.n + w - 1) / w * (uint64_t)it.spl, (uint32_t)i};
@@ -1309,6 +1320,7 @@ mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds,
     }
     b->count = count;
     b->recs.resize(count);
+    b->gs.resize(count);
     b->consumed.assign(count, 0);
     b->mexp.resize(count);
     for (uint32_t i = 0; i < count; i++)
@@ -1319,6 +1331,7 @@ mtgp_batch_t *mtgp_batch_create(const mtgp_param_set *ps, const uint32_t *seeds,
     uint64_t off = 0;
     for (uint32_t i = 0; i < count; i++) {
         b->recs[i] = make_record(&ps[i], off);
+        b->gs[i] = GenShape{b->recs[i].N, b->recs[i].M};
         off += b->recs[i].N;
     }
     std::vector<uint32_t> words(off);
