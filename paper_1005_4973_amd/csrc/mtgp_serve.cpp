@@ -65,6 +65,7 @@ struct PolyJob {
 };
 
 struct Req {
+    Req(uint64_t rid_, uint32_t gen_, uint32_t kind_, uint64_t n_) : rid(rid_), gen(gen_), kind(kind_), n(n_) {}
     uint64_t rid;
     uint32_t gen;
     uint32_t kind;
