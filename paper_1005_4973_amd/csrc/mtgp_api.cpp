@@ -933,10 +933,7 @@ int plan_split(mtgp_plan *p, std::vector<WorkItem> &items, std::vector<WorkItem>
             out.push_back(items[i]);
     items.swap(out);
     // the jump kernel is launched once per lane width and word-group count
-    std::stable_sort(jumps.begin(), jumps.end(), [](const JumpItem &x, const JumpItem &y) {
-        const JumpShape a = jump_shape(x.N), b = jump_shape(y.N);
-        return a.R != b.R ? a.R < b.R : a.G < b.G;
-    });
+    group_jumps_by_shape(jumps);
     // upload the polynomials (only their regions are meaningful)
     for (size_t i = 0; i < ok.size(); i++) {
         const uint32_t D = (uint32_t)b->psi[ok[i].gen].deg;

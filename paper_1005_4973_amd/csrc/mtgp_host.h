@@ -6,9 +6,28 @@
 #include "mtgp_f2.h"
 #include "mtgp_internal.h"
 
+#include <algorithm>
 #include <vector>
 
 namespace mtgp_impl {
+
+// Stable order of jump items by launch geometry (lane width R, then word
+// groups G): the jump kernel is launched once per (R, G). Sorts (key, index)
+// pairs and permutes, so no temporary JumpItem buffer (which the standard
+// library need not align to 32 bytes) is made.
+inline void group_jumps_by_shape(std::vector<JumpItem> &jumps)
+{
+    std::vector<std::pair<uint64_t, uint32_t>> key(jumps.size());
+    for (size_t i = 0; i < jumps.size(); i++) {
+        const JumpShape sh = jump_shape(jumps[i].N);
+        key[i] = {((uint64_t)sh.R << 32) | sh.G, (uint32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<JumpItem> out(jumps.size());
+    for (size_t i = 0; i < key.size(); i++)
+        out[i] = jumps[key[i].second];
+    jumps.swap(out);
+}
 
 // mtgp_batch_generate; with allow_split false a request is never turned into
 // jump-ahead segments, whatever the batch's split limit (the request loop's

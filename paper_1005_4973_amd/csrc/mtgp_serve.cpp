@@ -330,10 +330,7 @@ int launch_tick(mtgp_server *s)
                 r->job.reset();
             }
             // the jump kernel is launched once per lane width and word-group count
-            std::stable_sort(jumps.begin(), jumps.end(), [](const JumpItem &x, const JumpItem &y) {
-                const mtgp_impl::JumpShape a = mtgp_impl::jump_shape(x.N), b = mtgp_impl::jump_shape(y.N);
-                return a.R != b.R ? a.R < b.R : a.G < b.G;
-            });
+            mtgp_impl::group_jumps_by_shape(jumps);
             std::memcpy(h + jump_off, jumps.data(), jumps.size() * sizeof(JumpItem));
             const LaunchShape pshape = mtgp_impl::prefix_shape(s->b, pgens);
             for (size_t i = 0; i < starts.size(); i++)
