@@ -51,7 +51,13 @@ namespace f2 = mtgp_impl::f2;
 
 namespace {
 
-constexpr bool kSplitTicksEnabled = false;
+// Jump-ahead inside ticks is refused (mtgp_server_set_split); the CPU
+// self-test of the tick logic over a stand-in device builds this file with
+// MTGP_SERVE_SPLIT_TICKS=1. The library build never sets it.
+#ifndef MTGP_SERVE_SPLIT_TICKS
+#define MTGP_SERVE_SPLIT_TICKS 0
+#endif
+constexpr bool kSplitTicksEnabled = MTGP_SERVE_SPLIT_TICKS != 0;
 
 // Jump polynomials of one generator for segments of J outputs, laid out for
 // the jump kernel: entry 0 is the polynomial 1 (segment 0's copy), entry k

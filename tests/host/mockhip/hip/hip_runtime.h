@@ -1,7 +1,8 @@
 // Host-only stand-in for the HIP runtime header, for the request loop's CPU
-// self-test (tests/host/serve_selftest.cpp): events complete after a few
-// queries, copies are memcpy, allocations are calloc. Nothing here runs on a
-// GPU; the library itself is never built against it.
+// self-tests (tests/host/serve_selftest.cpp, tests/host/split_selftest.cpp):
+// events complete after a few queries, copies are memcpy, allocations are
+// calloc. Nothing here runs on a GPU; the library itself is never built
+// against it.
 #pragma once
 #include <cstddef>
 #include <cstdint>
@@ -15,6 +16,7 @@ enum { hipSuccess = 0, hipErrorNotReady = 600 };
 typedef struct ihipStream_t *hipStream_t;
 struct MockEvent {
     int polls_left;
+    bool reported;   // completion already seen by a query
 };
 typedef MockEvent *hipEvent_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
@@ -22,15 +24,30 @@ enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMe
 #define hipHostMallocDefault 0
 inline hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned)
 {
-    *e = new MockEvent{0};
+    *e = new MockEvent{0, true};
     return hipSuccess;
 }
 inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t)
 {
     e->polls_left = 2;
+    e->reported = false;
     return hipSuccess;
 }
-inline hipError_t hipEventQuery(hipEvent_t e) { return e->polls_left-- > 0 ? hipErrorNotReady : hipSuccess; }
+// called when a query first sees a recorded event complete (a test's hook)
+inline void (*mock_on_event_done)() = nullptr;
+inline hipError_t hipEventQuery(hipEvent_t e)
+{
+    if (e->polls_left > 0) {
+        e->polls_left--;
+        return hipErrorNotReady;
+    }
+    if (!e->reported) {
+        e->reported = true;
+        if (mock_on_event_done)
+            mock_on_event_done();
+    }
+    return hipSuccess;
+}
 inline hipError_t hipEventSynchronize(hipEvent_t e)
 {
     e->polls_left = 0;

@@ -2,7 +2,7 @@
 
 The library's device-free C++ sources (F2 polynomial arithmetic, the
 parameter search, the dimension of equidistribution), the request loop over a
-stand-in device, and the C oracle are
+stand-in device (with and without split ticks), and the C oracle are
 built with g++/gcc, -fsanitize=address,undefined and no recovery, and run
 their self-tests (tests/host/*): any leak, out-of-bounds access, overflow of
 a signed type or other undefined behaviour ends the run with an error.
@@ -43,6 +43,17 @@ def test_request_loop_under_sanitizers(tmp_path):
             os.path.join(CSRC, "mtgp_serve.cpp"), os.path.join(CSRC, "mtgp_f2.cpp")]
     build_and_run(tmp_path, "g++", srcs, ["-std=c++17", "-I", os.path.join(ROOT, "tests", "host", "mockhip"),
                                           "-I", os.path.join(ROOT, "include"), "-I", CSRC], "serve selftest ok")
+
+
+def test_split_ticks_under_sanitizers(tmp_path):
+    """The request loop's split ticks (refused by the library, built here with
+    MTGP_SERVE_SPLIT_TICKS=1) over the stand-in device: coverage, order,
+    segment flags and staging-ring disjointness."""
+    srcs = [os.path.join(ROOT, "tests", "host", "split_selftest.cpp"),
+            os.path.join(CSRC, "mtgp_serve.cpp"), os.path.join(CSRC, "mtgp_f2.cpp")]
+    build_and_run(tmp_path, "g++", srcs, ["-std=c++17", "-DMTGP_SERVE_SPLIT_TICKS=1",
+                                          "-I", os.path.join(ROOT, "tests", "host", "mockhip"),
+                                          "-I", os.path.join(ROOT, "include"), "-I", CSRC], "split selftest ok")
 
 
 def test_oracle_under_sanitizers(tmp_path):
