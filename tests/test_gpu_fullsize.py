@@ -239,3 +239,74 @@ def test_native_server_full_size(M):
         np.testing.assert_array_equal(b.get_state(g)[0], s, err_msg=f"state gen={g}")
     b.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_calls_beyond_2_32_outputs(M):
+    """The largest single calls: 2^32 + 65541 uint32 outputs (17.2 GB) in one
+    call, so that every count and offset on the path needs more than 32 bits.
+    Three paths over the same generator and seed: one generator without split
+    (one workgroup runs the whole call), the same with jump-ahead segments, and
+    a batch plan with a split limit. Each is compared with the oracle on the
+    first 4096 outputs, the 8192 around output 2^32, the last 1000, the end
+    state and consumed count, and a short call that continues the stream."""
+    import torch
+    n = (1 << 32) + 65541
+    ps = I.draw_param_sets([11213], 7100)[0]
+    seed = 4242
+    # windows [0, 4096), [2^32 - 4096, 2^32 + 4096), [n - 1000, n), in order
+    mid_at, tail_at = (1 << 32) - 4096, n - 1000
+    assert 4096 <= mid_at and mid_at + 8192 <= tail_at
+
+    def advance(st, k):
+        assert k >= 0
+        while k > 0:
+            step = min(k, 1 << 30)
+            O.advance(ps, st, step)
+            k -= step
+            say(f"oracle: {k} steps to the next window")
+
+    st = O.seed_state(seed, ps.mexp)
+    head = O.generate(ps, st, 4096)
+    advance(st, mid_at - 4096)
+    mid = O.generate(ps, st, 8192)
+    advance(st, tail_at - mid_at - 8192)
+    tail = O.generate(ps, st, 1000)
+    end_state = st.copy()
+    after = O.generate(ps, st, 3001)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def check(tag):
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(device_words(out, 0, 4096), head, err_msg=tag)
+        np.testing.assert_array_equal(device_words(out, mid_at, 8192), mid, err_msg=tag)
+        np.testing.assert_array_equal(device_words(out, tail_at, 1000), tail, err_msg=tag)
+
+    for split in (0, 1 << 14):
+        say(f"generator, split {split}")
+        out.zero_()
+        g = M.Generator(ps, seed)
+        if split:
+            g.set_split(split)
+        g.generate(n, M.KIND_UINT32, out)
+        check(f"generator split={split}")
+        words, consumed = g.get_state()
+        np.testing.assert_array_equal(words, end_state)
+        assert consumed == n
+        nxt = g.generate(3001, M.KIND_UINT32)
+        np.testing.assert_array_equal(nxt.cpu().numpy().view(np.uint32), after)
+        g.close()
+    say("batch plan, split 8192 rounds")
+    out.zero_()
+    b = M.Batch([ps], [seed])
+    b.set_split(8192)
+    p = b.plan([(0, M.KIND_UINT32, n, out.data_ptr())])
+    p.launch()
+    check("batch plan")
+    words, consumed = b.get_state(0)
+    np.testing.assert_array_equal(words, end_state)
+    assert consumed == n
+    p.close()
+    b.close()
+    del out
+    torch.cuda.empty_cache()
