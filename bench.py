@@ -545,7 +545,6 @@ def param_search(torch, I, mtgp, ctx):
     its tempering-parameter search; the sets here keep a random tempering
     matrix (that search is not done), so the figures are context, not a
     comparison."""
-    import threading
     threads = min(16, len(os.sched_getaffinity(0)))
     runs = []
     found = {}
@@ -556,17 +555,10 @@ def param_search(torch, I, mtgp, ctx):
         found[(mexp, ident)] = ps
         log(f"param_search: p={mexp} id={ident}: {runs[-1]}")
     # p = 23209: the seeded search accepts draw 40901 (about 20 ms of one
-    # core per candidate, most of it Berlekamp-Massey over 46k bits); the
-    # draw limit only bounds the run. A thread prints progress meanwhile.
+    # core per candidate, most of it Berlekamp-Massey over 46k bits; about
+    # 20 s on 16 cores); the draw limit only bounds the run.
     budget = 200000
-    done = threading.Event()
-
-    def progress():
-        t0 = time.perf_counter()
-        while not done.wait(20.0):
-            log(f"param_search: p=23209 search running, {time.perf_counter() - t0:.0f} s")
-    th = threading.Thread(target=progress, daemon=True)
-    th.start()
+    log("param_search: p=23209 search started")
     t0 = time.perf_counter()
     try:
         ps, st = mtgp.search_params(23209, id=1, seed=23209, max_draws=budget, threads=threads)
@@ -577,8 +569,6 @@ def param_search(torch, I, mtgp, ctx):
     except mtgp.MTGPError:
         runs.append({"mexp": 23209, "id": 1, "found": False, "draw_limit": budget,
                      "seconds": round(time.perf_counter() - t0, 1)})
-    finally:
-        done.set()
     log(f"param_search: p=23209 id=1: {runs[-1]}")
     # dimension of equidistribution of the found sets: one core, host only
     equi = []
