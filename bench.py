@@ -589,6 +589,42 @@ def param_search(torch, I, mtgp, ctx):
     return {"threads": threads, "runs": runs, "equidistribution": equi}
 
 
+def param_search_44497(torch, I, mtgp, ctx):
+    """Opt-in (minutes of host time, not in the default sections): the
+    recursion-parameter search at p = 44497 with ID 1, the largest released
+    size, then k(v) and Delta of the set found. The search runs as seeded
+    rounds of a fixed number of draws (seed 44497 + round), so each round
+    reports when it ends and the set found is fixed by the round schedule."""
+    threads = min(16, len(os.sched_getaffinity(0)))
+    per_round = 4000
+    rounds = []
+    t0 = time.perf_counter()
+    ps = None
+    for r in range(64):
+        try:
+            ps, st = mtgp.search_params(44497, id=1, seed=44497 + r, max_draws=per_round, threads=threads)
+        except mtgp.MTGPError:
+            rounds.append({"round": r, "found": False})
+            log(f"param_search_44497: round {r} ({per_round} draws) found none, "
+                f"{time.perf_counter() - t0:.0f} s")
+            continue
+        rounds.append({"round": r, "found": True, **st})
+        log(f"param_search_44497: round {r} found a set: {st}")
+        break
+    res = {"threads": threads, "draws_per_round": per_round, "rounds": len(rounds),
+           "seconds": round(time.perf_counter() - t0, 1), "last_round": rounds[-1]}
+    if ps is None:
+        return res
+    res["set"] = {"M": ps.pos, "sh1": ps.sh1, "sh2": ps.sh2, "param_tbl": list(ps.param_tbl),
+                  "temper_tbl": list(ps.temper_tbl)}
+    for name, tempered in (("tempered", True), ("untempered", False)):
+        t1 = time.perf_counter()
+        k, delta = mtgp.equidistribution(ps, tempered=tempered)
+        res[name] = {"delta": delta, "k_min": min(k), "k": list(k), "seconds": round(time.perf_counter() - t1, 2)}
+        log(f"param_search_44497: {name} delta {delta}")
+    return res
+
+
 def single_stream(torch, I, mtgp, ctx):
     """One generator, 2^20 uint32 per eager call: as one workgroup (the
     recursion's rounds in sequence), and split into jump-ahead segments (the
@@ -714,7 +750,8 @@ def main():
     sections = [s for s in args.sections.split(",") if s]
     fns = {"batched_plain": batched_plain, "independent_128": independent_128, "large_states": large_states,
            "large_states_wide_m": large_states_wide_m, "normals": normals,
-           "single_stream": single_stream, "serving": serving, "param_search": param_search}
+           "single_stream": single_stream, "serving": serving, "param_search": param_search,
+           "param_search_44497": param_search_44497}
     unknown = [name for name in sections if name not in fns]
     if unknown:
         raise SystemExit(f"unknown sections: {unknown}")
