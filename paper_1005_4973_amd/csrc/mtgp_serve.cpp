@@ -29,6 +29,7 @@
 // device.
 #include "../../include/mtgp.h"
 #include "mtgp_arena.h"
+#include "mtgp_ridmap.h"
 #include "mtgp_host.h"
 
 #include <hip/hip_runtime.h>
@@ -41,7 +42,6 @@
 #include <mutex>
 #include <new>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 using mtgp_impl::JumpItem;
@@ -72,6 +72,28 @@ struct PolyJob {
 
 struct Req {
     Req(uint64_t rid_, uint32_t gen_, uint32_t kind_, uint64_t n_) : rid(rid_), gen(gen_), kind(kind_), n(n_) {}
+    // a pooled request for a new submission: every field as the constructor
+    // leaves it (the segment vectors keep their capacity)
+    void reset(uint64_t rid_, uint32_t gen_, uint32_t kind_, uint64_t n_)
+    {
+        rid = rid_;
+        gen = gen_;
+        kind = kind_;
+        n = n_;
+        next = nullptr;
+        offset = 0;
+        blk = 0;
+        scheduled = 0;
+        finished = 0;
+        job.reset();
+        split = false;
+        S = 0;
+        slot = 0;
+        base = 0;
+        J = 0;
+        seg_len.clear();
+        seg_sched.clear();
+    }
     uint64_t rid;
     uint32_t gen;
     uint32_t kind;
@@ -122,7 +144,7 @@ struct mtgp_server {
     std::vector<Req *> req_pool;                           // released requests, for reuse
     std::deque<Tick> inflight;
     std::vector<hipEvent_t> spare_events;
-    std::unordered_map<uint64_t, Req *> completed;         // rid -> finished, not released
+    mtgp_impl::RidMap<Req> completed;                      // rid -> finished, not released
     std::deque<mtgp_completion> unreported;                // finished, not yet returned by poll
     std::vector<WorkItem> items;
     // jump-ahead
@@ -418,7 +440,7 @@ Req *new_req(mtgp_server *s, const mtgp_server_request &q)
     if (!s->req_pool.empty()) {
         r = s->req_pool.back();
         s->req_pool.pop_back();
-        *r = Req{q.rid, q.gen, q.kind, q.n};
+        r->reset(q.rid, q.gen, q.kind, q.n);
     } else {
         r = new (std::nothrow) Req{q.rid, q.gen, q.kind, q.n};
     }
@@ -533,7 +555,7 @@ int mtgp_server_poll(mtgp_server_t *s, mtgp_completion *done, uint32_t max_done,
                     r->split = false;
                 }
                 gq_remove(s, r);
-                s->completed[r->rid] = r;
+                s->completed.put(r->rid, r);
                 s->unreported.push_back(mtgp_completion{r->rid, r->offset, r->n});
             }
         }
@@ -573,14 +595,12 @@ int mtgp_server_release(mtgp_server_t *s, const uint64_t *rids, uint32_t count)
         return MTGP_EINVAL;
     int rc = MTGP_OK;
     for (uint32_t i = 0; i < count; i++) {
-        auto it = s->completed.find(rids[i]);
-        if (it == s->completed.end()) {
+        Req *r = s->completed.take(rids[i]);
+        if (!r) {
             rc = MTGP_EINVAL;
             continue;
         }
-        Req *r = it->second;
         s->index->give(r->blk);
-        s->completed.erase(it);
         s->req_pool.push_back(r);
     }
     return rc;
@@ -666,8 +686,7 @@ void mtgp_server_destroy(mtgp_server_t *s)
             delete r;
             r = nx;
         }
-    for (auto &kv : s->completed)
-        delete kv.second;
+    s->completed.for_each([](uint64_t, Req *r) { delete r; });
     for (Req *r : s->req_pool)
         delete r;
     (void)hipFree(s->d_pool);

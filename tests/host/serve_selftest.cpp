@@ -10,10 +10,12 @@
 #include "mtgp.h"
 #include "mtgp_arena.h"
 #include "mtgp_host.h"
+#include "mtgp_ridmap.h"
 
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <unordered_map>
 #include <vector>
 
 struct mtgp_batch {
@@ -227,8 +229,52 @@ static void test_arena_index()
     std::printf("arena index checked\n");
 }
 
+// The id map against std::unordered_map: random puts (new ids and
+// replacements) and takes (present and absent ids), over sequential ids,
+// ids in one residue class (equal low bits) and random ids, through several
+// table growths; after each phase every entry is checked and the map drained.
+static void test_rid_map()
+{
+    static int objs[1 << 16];
+    for (int pattern = 0; pattern < 3; pattern++) {
+        mtgp_impl::RidMap<int> m;
+        std::unordered_map<uint64_t, int *> model;
+        auto id_of = [&](uint64_t k) -> uint64_t {
+            return pattern == 0 ? k : pattern == 1 ? (k << 20) : (k * 0x9e3779b97f4a7c15ull) ^ 0x5555;
+        };
+        for (int step = 0; step < 200000; step++) {
+            const uint64_t k = rnd() % 40000;
+            const uint64_t rid = id_of(k);
+            if (rnd() % 2) {
+                int *p = &objs[rnd() % (1 << 16)];
+                m.put(rid, p);
+                model[rid] = p;
+            } else {
+                auto it = model.find(rid);
+                int *want = it == model.end() ? nullptr : it->second;
+                CHECK(m.take(rid) == want, "take of id %llu (pattern %d)", (unsigned long long)rid, pattern);
+                if (it != model.end())
+                    model.erase(it);
+            }
+            CHECK(m.size() == model.size(), "size %zu against %zu", m.size(), model.size());
+        }
+        size_t seen = 0;
+        m.for_each([&](uint64_t rid, int *p) {
+            seen++;
+            auto it = model.find(rid);
+            CHECK(it != model.end() && it->second == p, "entry %llu", (unsigned long long)rid);
+        });
+        CHECK(seen == model.size(), "for_each visits %zu of %zu", seen, model.size());
+        for (auto &kv : model)
+            CHECK(m.take(kv.first) == kv.second, "drain %llu", (unsigned long long)kv.first);
+        CHECK(m.size() == 0, "drained map not empty");
+    }
+    std::printf("rid map checked\n");
+}
+
 int main()
 {
+    test_rid_map();
     test_arena_index();
     run_stream(64, 3000, 300000, 1 << 14, 2, 64ull << 20);
     run_stream(8, 2000, 300000, 1 << 12, 3, 64ull << 20);
