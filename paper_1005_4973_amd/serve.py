@@ -341,6 +341,22 @@ class NativeServer:
         reqs["kind"] = k_in
         t_done = np.full(count, np.nan)
         self.kept = {}
+        # the loop calls the library directly with pointers taken once (no
+        # per-call slicing, pointer objects or copies of the completions)
+        import ctypes
+        L = self.mtgp.lib()
+        submit_fn, poll_fn, release_fn = L.mtgp_server_submit, L.mtgp_server_poll, L.mtgp_server_release
+        h = self._h
+        base = reqs.ctypes.data
+        size = reqs.dtype.itemsize
+        done_arr = self._done
+        done_ptr = done_arr.ctypes.data_as(ctypes.POINTER(self.mtgp.CompletionC))
+        cap = len(done_arr)
+        ndone = ctypes.c_uint32(0)
+        ndone_ref = ctypes.byref(ndone)
+        rel = np.zeros(cap, dtype=np.uint64)
+        rel_ptr = rel.ctypes.data
+        check = self.mtgp._check
         t0 = clock()
         i = 0
         outstanding = 0
@@ -348,13 +364,16 @@ class NativeServer:
             now = clock() - t0
             j = int(np.searchsorted(arrival, now, side="right")) if realtime else count
             if j > i:
-                self.submit(reqs[i:j])
+                check(submit_fn(h, base + i * size, j - i), "mtgp_server_submit")
                 outstanding += j - i
                 i = j
-            done = self.poll()
-            if len(done):
-                t_done[done["rid"].astype(np.int64)] = clock() - t0
-                outstanding -= len(done)
+            check(poll_fn(h, done_ptr, cap, ndone_ref), "mtgp_server_poll")
+            nd = ndone.value
+            if nd:
+                done = done_arr[:nd]
+                rid = done["rid"]
+                t_done[rid] = clock() - t0
+                outstanding -= nd
                 if on_complete is not None:
                     for c in done:
                         on_complete(int(c["rid"]), self.output(int(c["offset"]), int(c["n"])))
@@ -362,7 +381,8 @@ class NativeServer:
                     for c in done:
                         self.kept[int(c["rid"])] = (int(c["offset"]), int(c["n"]))
                 else:
-                    self.release(done["rid"])
+                    rel[:nd] = rid
+                    check(release_fn(h, rel_ptr, nd), "mtgp_server_release")
             elif outstanding > 0:
                 if keep:
                     waiting, active, inflight = self.pending()
