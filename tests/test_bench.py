@@ -84,3 +84,15 @@ def test_roofline_block_fractions(bench):
     assert blk["end_to_end"]["frac"] == 0.4
     assert blk["frac_of_store_ceiling"] == round(4000.0 / 6000.0, 4)
     assert blk["kernel"] == "mtgp_chunk_kernel<2048, 2, 1>" and blk["launch"] == LAUNCH
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    """--gpus N > 1 ends with a message and a non-zero status, and without a
+    GPU (this test runs on the CPU), so nothing was set up on a device first."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0
+    assert "one GPU only" in res.stderr and "--gpus 2" in res.stderr
+    assert res.stdout == ""
