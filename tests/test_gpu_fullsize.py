@@ -245,9 +245,10 @@ def test_native_server_full_size(M):
 def test_calls_beyond_2_32_outputs(M):
     """The largest single calls: 2^32 + 65541 uint32 outputs (17.2 GB) in one
     call, so that every count and offset on the path needs more than 32 bits.
-    Three paths over the same generator and seed: one generator without split
-    (one workgroup runs the whole call), the same with jump-ahead segments, and
-    a batch plan with a split limit. Each is compared with the oracle on the
+    Five paths over the same generator and seed: one generator without split
+    in each of the three launch forms (one workgroup, one wavefront, the
+    chunked wavefront form run the whole call), the same with jump-ahead
+    segments, and a batch plan with a split limit. Each is compared with the oracle on the
     first 4096 outputs, the 8192 around output 2^32, the last 1000, the end
     state and consumed count, and a short call that continues the stream."""
     import torch
@@ -282,14 +283,18 @@ def test_calls_beyond_2_32_outputs(M):
         np.testing.assert_array_equal(device_words(out, mid_at, 8192), mid, err_msg=tag)
         np.testing.assert_array_equal(device_words(out, tail_at, 1000), tail, err_msg=tag)
 
-    for split in (0, 1 << 14):
-        say(f"generator, split {split}")
+    # (mode, lanes, steps per lane or read-ahead): workgroup form, wavefront
+    # form, chunked form (N - M = 280 for this set, enough for read-ahead 2)
+    for split, launch in ((0, None), (0, (1, 64, 4)), (0, (2, 64, 2)), (1 << 14, None)):
+        say(f"generator, split {split}, launch {launch}")
         out.zero_()
         g = M.Generator(ps, seed)
         if split:
             g.set_split(split)
+        if launch:
+            g.set_launch(*launch, 0)
         g.generate(n, M.KIND_UINT32, out)
-        check(f"generator split={split}")
+        check(f"generator split={split} launch={launch}")
         words, consumed = g.get_state()
         np.testing.assert_array_equal(words, end_state)
         assert consumed == n
